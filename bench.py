@@ -1,0 +1,173 @@
+"""Throughput benchmark of the MI355X parameter-scan Monte Carlo.
+
+A step is one whole scan of the two-parameter Gaussian grid (1000 x 1000
+points, y in [0,1]^3, 2^14 samples per point, Philox seed 42) on one GPU:
+planning, point decoding, Philox words, uniform map, integrand, per-lane
+Kahan sums, FP64 merges, split merge and the f / sigma writes.  The parameter
+lists and the output buffers are resident in HBM before the timed region.
+
+Prints ONE JSON line on stdout.  Extra fields: the FP64 path on the same
+workload, per-step latency percentiles, the roofline of the main kernel
+(VALU-bound; algorithmic lane-operations per sample stated in the design doc),
+and the CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MC samples/s & grid pts/s on 1 MI355X (fp32 vs fp64); p50/p99 scan latency"
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes per clock at 2.4 GHz = one 32-bit VALU
+# lane-operation slot per lane per clock (the FP32 vector peak of 157.3
+# TFLOP/s counts a packed FMA as 4 FLOP in one such slot).
+VALU_PEAK = 256 * 64 * 2.4e9
+
+
+def valu_ops_per_sample(family, N, precision):
+    """Algorithmic VALU issue slots per sample (full-rate = 1, the measured
+    half-rate transcendentals = 2): Philox 2.5N rounds x (2 wide multiplies +
+    2 three-way xors), N conversions + N map FMAs, the integrand, and 8 for
+    the compensated accumulation."""
+    rng = 2.5 * N * 4
+    mapping = 2 * N
+    if family == "gauss":
+        integrand = 2 * N + 2
+    elif family == "sin_sum":
+        integrand = N + 2
+    elif family == "cosexp":
+        integrand = 2 + (N - 2) + 2 + 2 + 2 + 1
+    else:
+        integrand = N
+    acc = 8
+    w = rng + mapping + integrand + acc
+    return float(w if precision == "fp32" else w)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_path(spec, steps, warmup):
+    import torch
+    from paper_1910_01965_amd import zmc
+    G = zmc.validate(spec)
+    d_axis = zmc.axis_tensor(spec)
+    f = torch.empty(G, dtype=torch.float64, device="cuda")
+    s = torch.empty(G, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        zmc.scan_device(spec, d_axis, f, s, stream=stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    step_ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    for a, b in ev:  # create the underlying HIP events
+        a.record(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_ev[0].record(stream)
+    for i in range(steps):
+        zmc.scan_device(spec, d_axis, f, s, stream=stream,
+                        events=(ev[i][0].cuda_event, ev[i][1].cuda_event))
+        step_ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    step_ms = np.array([step_ev[i].elapsed_time(step_ev[i + 1]) for i in range(steps)])
+    ok = bool(torch.isfinite(f).all()) and bool(torch.isfinite(s).all())
+    return dict(wall_s=wall, kernel_ms=kernel_ms, step_ms=step_ms, finite=ok,
+                plan=zmc.plan(spec))
+
+
+def cpu_baseline(spec, points, seed=0):
+    from oracle import oracle as zo
+    idx = np.sort(np.random.default_rng(seed).choice(spec.G, points, replace=False)).astype(np.uint64)
+    t0 = time.perf_counter()
+    zo.scan(spec.with_(precision="fp64"), idx)
+    dt = time.perf_counter() - t0
+    return {"value": points * spec.samples / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"{points} seeded random grid points of {spec.name} (all {spec.samples} samples "
+                      f"each, {points * spec.samples:.3g} samples), single-threaded FP64 oracle, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--cpu-points", type=int, default=12000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the scan shards by "
+              "grid-point ranges across GPUs with no exchange, which this build does not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1910_01965_amd import workloads as wl
+    from paper_1910_01965_amd import zmc
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    zmc.load()
+
+    spec = wl.gauss_2p(precision="fp32")
+    G, n = spec.G, spec.samples
+    log(f"bench: {spec.name} fp32, warmup {args.warmup}, steps {args.steps}")
+    r32 = time_path(spec, args.steps, args.warmup)
+    ms_per_step = r32["wall_s"] * 1e3 / args.steps
+    value = G * n / (ms_per_step / 1e3)
+    kern_ms = float(np.mean(r32["kernel_ms"]))
+    log(f"fp32: {ms_per_step:.3f} ms/step, kernel {kern_ms:.3f} ms, {value:.4g} samples/s")
+
+    spec64 = spec.with_(precision="fp64")
+    log(f"bench: {spec.name} fp64, steps {args.fp64_steps}")
+    r64 = time_path(spec64, args.fp64_steps, 1)
+    ms64 = r64["wall_s"] * 1e3 / args.fp64_steps
+    log(f"fp64: {ms64:.3f} ms/step")
+
+    w = valu_ops_per_sample(spec.family, spec.N, "fp32")
+    achieved = w * G * n / (kern_ms / 1e3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                "ops_per_sample": w, "kernel": "k_point_major<Gauss<float,3>>",
+                "kernel_ms": kern_ms}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": spec.name, "grid_points": G, "samples_per_point": n, "N": spec.N,
+                   "family": spec.family, "precision": "fp32 evaluation, fp64 merge", "seed": spec.seed,
+                   "plan": r32["plan"]},
+        "grid_pts_per_s": G / (ms_per_step / 1e3),
+        "fp64": {"value": G * n / (ms64 / 1e3), "unit": "samples/s", "ms_per_step": ms64,
+                 "grid_pts_per_s": G / (ms64 / 1e3), "steps": args.fp64_steps},
+        "latency_ms": {"p50": float(np.percentile(r32["step_ms"], 50)),
+                       "p99": float(np.percentile(r32["step_ms"], 99)),
+                       "what": "per-scan device time of back-to-back plain scans"},
+        "roofline": roofline,
+        "finite": r32["finite"] and r64["finite"],
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on {args.cpu_points} points")
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_points)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * zmc.h -- C ABI of the MI355X (gfx950) direct Monte Carlo parameter-scan
+ * library, libzmc.so.
+ *
+ * The operation (ZMCintegral-v5, arXiv:1910.01965, Sec. 2, Eq. (1)): for every
+ * point x of an M-dimensional parameter grid, each parameter x_l running over
+ * its own list of values, estimate f(x) = integral of g(y; x) dy over an
+ * N-dimensional box by direct (crude) Monte Carlo (Sec. 1 and Sec. 2: no
+ * stratification, no adaptive tree search), and return the whole grid of
+ * results (Sec. 2, last paragraph; Sec. 3.3).  Each point's estimate is
+ *     f     = V * (1/n) sum_s g(y_s; x)
+ *     sigma = V * sqrt( sum_s (g_s - mean)^2 / (n (n-1)) )
+ * with V the box volume.  The paper names no random generator and reports no
+ * error bar; this library fixes both:
+ *   - sample s, coordinate k of grid point g uses word w = s*N + k of the
+ *     Philox4x32-10 stream (Salmon et al., SC'11) with key = seed and counter
+ *     (b mod 2^32, b / 2^32, g mod 2^32, g / 2^32), b = w / 4, lane w mod 4;
+ *   - FP64 path: u = (r + 1/2) 2^-32, y_k = fma(hi_k - lo_k, u, lo_k);
+ *     FP32 path: u = ((r >> 9) + 1/2) 2^-23 from the top 23 bits.
+ * Results therefore do not depend on how the library splits the work.
+ *
+ * Grid flattening is C order: flat index g = ((i_1 L_2 + i_2) L_3 + ...) L_M
+ * + i_M (the last parameter varies fastest); outputs are indexed by g.
+ *
+ * Conventions for every entry point:
+ *   - the return value is a zmc_status; nothing is thrown or aborted across
+ *     the ABI; zmc_last_error() gives a message for the calling thread;
+ *   - pointers named d_* are device (HBM) pointers on the current HIP device;
+ *     other pointers are host memory; all are owned by the caller and read or
+ *     written only during the call (for asynchronous calls: until the work on
+ *     the given stream has completed);
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ */
+#ifndef ZMC_H
+#define ZMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum zmc_status {
+  ZMC_OK = 0,
+  ZMC_E_INVALID = 1,     /* malformed descriptor or argument              */
+  ZMC_E_NOMEM = 2,       /* device or host allocation failed              */
+  ZMC_E_DEVICE = 3,      /* a HIP call failed (no device, launch error)   */
+  ZMC_E_UNSUPPORTED = 4, /* valid request this build does not implement   */
+  ZMC_E_BUSY = 5         /* resource limit reached; retry later           */
+} zmc_status;
+
+/* Integrand families, compiled in as templates.  SIN_SUM is the paper's test
+ * integrand (Eq. (2) on [0,10]^N, Eq. (4) on [0,1]^6). */
+typedef enum zmc_family {
+  ZMC_SIN_SUM = 0, /* sin(sum_{l=1..M} x_l + sum_{k=1..N} y_k), any M          */
+  ZMC_GAUSS = 1,   /* exp(-(sum_{k<=M} x_k y_k^2 + sum_{k>M} y_k^2)), M <= N   */
+  ZMC_COSEXP = 2,  /* cos(x1 y1 + x2 y2 + sum_{k>=3} y_k) exp(-x3^2 y1 y2) + x4,
+                      M = 4, N >= 2                                             */
+  ZMC_CONST = 3,   /* 1 (sampler and estimator check)                          */
+  ZMC_LINEAR = 4   /* sum_k y_k (sampler and estimator check)                  */
+} zmc_family;
+
+typedef enum zmc_precision {
+  ZMC_FP64 = 0,         /* FP64 sampling, integrand and accumulation         */
+  ZMC_FP32_MERGE64 = 1  /* FP32 integrand and per-lane Kahan-compensated sums,
+                           FP64 merging across lanes, waves, blocks, splits  */
+} zmc_precision;
+
+/* One scan.  Limits: 0 <= M <= 16; 1 <= N <= 8 (N <= 16 is a valid
+ * descriptor, N > 8 returns ZMC_E_UNSUPPORTED); every axis_len >= 1;
+ * G = prod axis_len <= 2^62; lo_k < hi_k, both finite; samples >= 2 and
+ * samples * N <= 2^62; n_params = 0 for the five families above. */
+typedef struct zmc_scan_desc {
+  int32_t M;                /* number of parameters                          */
+  int32_t N;                /* integration dimensions                        */
+  const int64_t* axis_len;  /* [M] list lengths L_l                          */
+  const double* axis_vals;  /* [sum L_l] host copy of the lists, back to back;
+                               may be NULL for zmc_scan_device              */
+  const double* lo;         /* [N] lower box edges                           */
+  const double* hi;         /* [N] upper box edges                           */
+  int32_t family;           /* zmc_family                                    */
+  int32_t precision;        /* zmc_precision                                 */
+  const double* params;     /* [n_params] extra family parameters (unused)   */
+  int32_t n_params;
+  uint64_t samples;         /* n, samples per grid point                     */
+  uint64_t seed;            /* Philox key                                    */
+} zmc_scan_desc;
+
+/* Work decomposition.  Zero fields mean "choose automatically".  The results
+ * do not depend on these beyond floating-point summation order. */
+typedef enum zmc_mode {
+  ZMC_MODE_AUTO = 0,
+  ZMC_MODE_POINT_MAJOR = 1,  /* each lane owns one point, a wave 64 points;
+                                sample range optionally cut into splits       */
+  ZMC_MODE_SAMPLE_MAJOR = 2  /* a block owns one point; its lanes share the
+                                samples; wave then LDS reduction; optionally
+                                several blocks per point (splits)             */
+} zmc_mode;
+
+typedef struct zmc_launch_opts {
+  int32_t mode;          /* zmc_mode                                          */
+  int32_t block;         /* threads per block: 64..1024 (point-major: ..256),
+                            multiple of 64                                    */
+  int32_t splits;        /* sample-range pieces per point (>= 1)              */
+  int32_t cu_count;      /* planner only: compute units assumed (0 = device)  */
+  void* ev_begin;        /* optional hipEvent_t recorded on the stream just
+                            before the main scan kernel (for timing)          */
+  void* ev_end;          /* optional hipEvent_t recorded just after it, before
+                            the split-merge pass                              */
+} zmc_launch_opts;
+
+typedef struct zmc_plan_info {
+  int32_t mode;              /* chosen zmc_mode                               */
+  int32_t block;             /* threads per block                             */
+  int32_t splits;            /* sample-range pieces per point                 */
+  int32_t reserved;
+  uint64_t grid_points;      /* G                                             */
+  uint64_t groups;           /* ceil(samples / 4): groups of four samples     */
+  uint64_t groups_per_split; /* groups in each piece (the last may be short)  */
+  uint64_t blocks;           /* blocks of the main kernel                     */
+  uint64_t workspace_bytes;  /* device bytes of split partials (0 if none)    */
+} zmc_plan_info;
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* zmc_last_error(void);
+
+/* Library version string. */
+const char* zmc_version(void);
+
+/* Host-only validation of a descriptor (no device use).  Returns ZMC_OK,
+ * ZMC_E_INVALID or ZMC_E_UNSUPPORTED; *grid_points (if not NULL) gets G. */
+zmc_status zmc_validate(const zmc_scan_desc* desc, uint64_t* grid_points);
+
+/* Host-only work decomposition that zmc_scan_device_ex would use with these
+ * options (opts may be NULL).  Without opts->cu_count, queries the current
+ * device's compute-unit count (ZMC_E_DEVICE if there is none). */
+zmc_status zmc_plan(const zmc_scan_desc* desc, const zmc_launch_opts* opts,
+                    zmc_plan_info* out);
+
+/* Synchronous scan with host memory: stages desc->axis_vals to the device,
+ * computes, copies f and sigma (G doubles each, C order) back into the
+ * caller's host arrays.  On error the outputs are unspecified. */
+zmc_status zmc_scan(const zmc_scan_desc* desc, double* f, double* sigma);
+
+/* Asynchronous scan on `stream` with device-resident data: d_axis_vals holds
+ * the concatenated value lists (sum L_l doubles; may be NULL when M = 0);
+ * d_f and d_sigma receive G doubles each.  desc->axis_vals is not read.
+ * Split partials, when the plan needs them, live in stream-ordered device
+ * memory that is released on the same stream.  Returns after enqueueing. */
+zmc_status zmc_scan_device(const zmc_scan_desc* desc, const double* d_axis_vals,
+                           double* d_f, double* d_sigma, void* stream);
+
+/* zmc_scan_device with an explicit decomposition (opts may be NULL). */
+zmc_status zmc_scan_device_ex(const zmc_scan_desc* desc, const double* d_axis_vals,
+                              double* d_f, double* d_sigma,
+                              const zmc_launch_opts* opts, void* stream);
+
+/* Debug: words w0 .. w0+count-1 of grid point g's Philox stream, computed by
+ * the device generator, into d_out (count uint32).  Asynchronous. */
+zmc_status zmc_debug_words(uint64_t seed, uint64_t g, uint64_t w0, int64_t count,
+                           uint32_t* d_out, void* stream);
+
+/* Debug: integrand values g(y_s; x_g) for samples s = s0 .. s0+count-1 of
+ * grid point g, computed by the device sampler and integrand in the
+ * descriptor's precision and widened to FP64, into d_out (count doubles). */
+zmc_status zmc_debug_values(const zmc_scan_desc* desc, const double* d_axis_vals,
+                            uint64_t g, uint64_t s0, int64_t count, double* d_out,
+                            void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZMC_H */

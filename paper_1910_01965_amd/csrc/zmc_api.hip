@@ -1,0 +1,342 @@
+// zmc_api.hip -- host side of libzmc: descriptor validation, the work
+// planner, and the C ABI entry points declared in include/zmc.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "zmc.h"
+#include "zmc_device.hpp"
+#include "zmc_internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+zmc_status fail(zmc_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+zmc_status ok() {
+  g_err[0] = '\0';
+  return ZMC_OK;
+}
+
+#define ZMC_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(e_ == hipErrorOutOfMemory ? ZMC_E_NOMEM : ZMC_E_DEVICE,          \
+                  "%s failed: %s", #call, hipGetErrorString(e_));                  \
+  } while (0)
+
+constexpr uint64_t kMaxG = (uint64_t)1 << 62;
+
+// Validation rules of the descriptor (include/zmc.h).
+zmc_status validate(const zmc_scan_desc* d, uint64_t* G_out) {
+  if (d == nullptr) return fail(ZMC_E_INVALID, "descriptor is NULL");
+  if (d->M < 0 || d->M > zmc::kMaxParams)
+    return fail(ZMC_E_INVALID, "M = %d outside 0..%d", d->M, zmc::kMaxParams);
+  if (d->M > 0 && d->axis_len == nullptr) return fail(ZMC_E_INVALID, "axis_len is NULL with M > 0");
+  uint64_t G = 1;
+  for (int l = 0; l < d->M; ++l) {
+    const int64_t L = d->axis_len[l];
+    if (L < 1) return fail(ZMC_E_INVALID, "axis_len[%d] = %lld < 1", l, (long long)L);
+    if (G > kMaxG / (uint64_t)L) return fail(ZMC_E_INVALID, "grid larger than 2^62 points");
+    G *= (uint64_t)L;
+  }
+  if (d->N < 1 || d->N > 16) return fail(ZMC_E_INVALID, "N = %d outside 1..16", d->N);
+  if (d->lo == nullptr || d->hi == nullptr) return fail(ZMC_E_INVALID, "lo or hi is NULL");
+  for (int k = 0; k < d->N; ++k) {
+    if (!isfinite(d->lo[k]) || !isfinite(d->hi[k]))
+      return fail(ZMC_E_INVALID, "box edge %d is not finite", k);
+    if (!(d->lo[k] < d->hi[k])) return fail(ZMC_E_INVALID, "box edge %d: lo >= hi", k);
+  }
+  if (d->samples < 2) return fail(ZMC_E_INVALID, "samples = %llu < 2", (unsigned long long)d->samples);
+  if (d->samples > kMaxG / (uint64_t)d->N) return fail(ZMC_E_INVALID, "samples * N exceeds 2^62");
+  switch (d->family) {
+    case ZMC_SIN_SUM:
+    case ZMC_CONST:
+    case ZMC_LINEAR:
+      break;
+    case ZMC_GAUSS:
+      if (d->M > d->N) return fail(ZMC_E_INVALID, "GAUSS needs M <= N (M = %d, N = %d)", d->M, d->N);
+      break;
+    case ZMC_COSEXP:
+      if (d->M != 4 || d->N < 2)
+        return fail(ZMC_E_INVALID, "COSEXP needs M = 4 and N >= 2 (M = %d, N = %d)", d->M, d->N);
+      break;
+    default:
+      return fail(ZMC_E_INVALID, "unknown family %d", d->family);
+  }
+  if (d->precision != ZMC_FP64 && d->precision != ZMC_FP32_MERGE64)
+    return fail(ZMC_E_INVALID, "unknown precision %d", d->precision);
+  if (d->n_params != 0) return fail(ZMC_E_INVALID, "n_params = %d; these families take none", d->n_params);
+  if (d->N > zmc::kMaxDims)
+    return fail(ZMC_E_UNSUPPORTED, "N = %d > %d is not built", d->N, zmc::kMaxDims);
+  if (G_out) *G_out = G;
+  return ok();
+}
+
+std::mutex g_cu_mu;
+std::vector<int> g_cu_cache;
+
+zmc_status device_cu_count(int* cu) {
+  int dev = 0;
+  ZMC_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_cu_mu);
+    if ((int)g_cu_cache.size() > dev && g_cu_cache[dev] > 0) {
+      *cu = g_cu_cache[dev];
+      return ZMC_OK;
+    }
+  }
+  int v = 0;
+  ZMC_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev));
+  if (v <= 0) return fail(ZMC_E_DEVICE, "device reports %d compute units", v);
+  std::lock_guard<std::mutex> lk(g_cu_mu);
+  if ((int)g_cu_cache.size() <= dev) g_cu_cache.resize(dev + 1, 0);
+  g_cu_cache[dev] = v;
+  *cu = v;
+  return ZMC_OK;
+}
+
+uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Work planner.  Point-major when the grid alone gives every SIMD at least one
+// wave; the sample range is then cut into enough pieces that the launch holds
+// ~16 waves per wave slot (so the last round of blocks is a small fraction
+// of the run), each piece keeping >= 64 groups (256 samples) per lane.
+// Otherwise sample-major with enough blocks per point for ~4 waves per slot
+// and >= 16 groups per lane.
+constexpr uint64_t kMaxGridX = (uint64_t)1 << 30;
+constexpr int kMaxSplits = 65535;
+constexpr uint64_t kMaxWorkspace = (uint64_t)8 << 30;
+
+zmc_status make_plan(const zmc_scan_desc* d, uint64_t G, const zmc_launch_opts* o, zmc::Plan* pl) {
+  int cu = (o && o->cu_count > 0) ? o->cu_count : 0;
+  if (cu == 0) {
+    zmc_status st = device_cu_count(&cu);
+    if (st != ZMC_OK) return st;
+  }
+  const uint64_t slots = (uint64_t)cu * 4 * 8;  // wave slots: 4 SIMDs x 8 waves
+  const uint64_t groups = cdiv(d->samples, 4);
+  int mode = o ? o->mode : ZMC_MODE_AUTO;
+  if (mode == ZMC_MODE_AUTO)
+    mode = (G >= (uint64_t)cu * 4 * 64) ? ZMC_MODE_POINT_MAJOR : ZMC_MODE_SAMPLE_MAJOR;
+  if (mode != ZMC_MODE_POINT_MAJOR && mode != ZMC_MODE_SAMPLE_MAJOR)
+    return fail(ZMC_E_INVALID, "unknown mode %d", mode);
+  int block = (o && o->block > 0) ? o->block : 256;
+  if (block < 64 || block > 1024 || block % 64 != 0)
+    return fail(ZMC_E_INVALID, "block = %d: needs a multiple of 64 in 64..1024", block);
+  if (mode == ZMC_MODE_POINT_MAJOR && block > 256)
+    return fail(ZMC_E_INVALID, "point-major blocks hold at most 256 threads");
+  uint64_t splits = (o && o->splits > 0) ? (uint64_t)o->splits : 0;
+  if (splits == 0) {
+    if (mode == ZMC_MODE_POINT_MAJOR) {
+      const uint64_t waves = cdiv(G, 64);
+      splits = cdiv(16 * slots, waves);
+      uint64_t cap = groups / 64;
+      if (cap < 1) cap = 1;
+      if (splits > cap) splits = cap;
+    } else {
+      const uint64_t waves = G * (uint64_t)(block / 64);
+      splits = cdiv(4 * slots, waves);
+      uint64_t cap = groups / ((uint64_t)block * 16);
+      if (cap < 1) cap = 1;
+      if (splits > cap) splits = cap;
+    }
+    if (splits < 1) splits = 1;
+    while (splits > 1 && 16.0 * (double)splits * (double)G > (double)kMaxWorkspace) splits /= 2;
+  }
+  if (splits > (uint64_t)kMaxSplits) splits = kMaxSplits;
+  if (splits > groups) splits = groups;
+  const uint64_t gps = cdiv(groups, splits);
+  splits = cdiv(groups, gps);  // no empty piece
+  pl->mode = mode;
+  pl->block = block;
+  pl->splits = (int)splits;
+  pl->groups = groups;
+  pl->gps = gps;
+  pl->point_blocks = cdiv(G, (uint64_t)block);
+  const uint64_t gx = (mode == ZMC_MODE_POINT_MAJOR) ? pl->point_blocks : G;
+  pl->grid_x = gx < kMaxGridX ? gx : kMaxGridX;
+  pl->workspace_bytes = splits > 1 ? 16 * splits * G : 0;
+  return ZMC_OK;
+}
+
+void fill_params(const zmc_scan_desc* d, uint64_t G, const zmc::Plan& pl, const double* d_axis,
+                 double* d_f, double* d_sigma, zmc::ScanParams* p) {
+  memset(p, 0, sizeof(*p));
+  p->G = G;
+  p->n = d->samples;
+  p->n_groups = pl.groups;
+  p->gps = pl.gps;
+  p->seed = d->seed;
+  p->point_blocks = pl.point_blocks;
+  p->M = d->M;
+  p->N = d->N;
+  p->splits = pl.splits;
+  p->family = d->family;
+  int64_t off = 0;
+  uint64_t stride = 1;
+  for (int l = d->M - 1; l >= 0; --l) {
+    p->axis_stride[l] = stride;
+    stride *= (uint64_t)d->axis_len[l];
+  }
+  for (int l = 0; l < d->M; ++l) {
+    p->axis_len[l] = d->axis_len[l];
+    p->axis_off[l] = off;
+    off += d->axis_len[l];
+  }
+  double vol = 1.0;
+  for (int k = 0; k < d->N; ++k) {
+    p->lo[k] = d->lo[k];
+    p->hi[k] = d->hi[k];
+    vol *= d->hi[k] - d->lo[k];
+  }
+  p->vol = vol;
+  p->axis = d_axis;
+  p->f = d_f;
+  p->sigma = d_sigma;
+}
+
+void to_info(const zmc::Plan& pl, uint64_t G, zmc_plan_info* out) {
+  memset(out, 0, sizeof(*out));
+  out->mode = pl.mode;
+  out->block = pl.block;
+  out->splits = pl.splits;
+  out->grid_points = G;
+  out->groups = pl.groups;
+  out->groups_per_split = pl.gps;
+  out->blocks = pl.grid_x * (uint64_t)pl.splits;
+  out->workspace_bytes = pl.workspace_bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* zmc_last_error(void) { return g_err; }
+
+const char* zmc_version(void) { return "zmc 0.1 gfx950"; }
+
+zmc_status zmc_validate(const zmc_scan_desc* desc, uint64_t* grid_points) {
+  return validate(desc, grid_points);
+}
+
+zmc_status zmc_plan(const zmc_scan_desc* desc, const zmc_launch_opts* opts, zmc_plan_info* out) {
+  uint64_t G = 0;
+  zmc_status st = validate(desc, &G);
+  if (st != ZMC_OK) return st;
+  if (out == nullptr) return fail(ZMC_E_INVALID, "out is NULL");
+  zmc::Plan pl;
+  st = make_plan(desc, G, opts, &pl);
+  if (st != ZMC_OK) return st;
+  to_info(pl, G, out);
+  return ok();
+}
+
+zmc_status zmc_scan_device_ex(const zmc_scan_desc* desc, const double* d_axis_vals, double* d_f,
+                              double* d_sigma, const zmc_launch_opts* opts, void* stream) {
+  uint64_t G = 0;
+  zmc_status st = validate(desc, &G);
+  if (st != ZMC_OK) return st;
+  if (desc->M > 0 && d_axis_vals == nullptr) return fail(ZMC_E_INVALID, "d_axis_vals is NULL with M > 0");
+  if (d_f == nullptr || d_sigma == nullptr) return fail(ZMC_E_INVALID, "d_f or d_sigma is NULL");
+  zmc::Plan pl;
+  st = make_plan(desc, G, opts, &pl);
+  if (st != ZMC_OK) return st;
+  zmc::ScanParams p;
+  fill_params(desc, G, pl, d_axis_vals, d_f, d_sigma, &p);
+  hipStream_t s = (hipStream_t)stream;
+  void* ws = nullptr;
+  if (pl.workspace_bytes > 0) {
+    ZMC_HIP(hipMallocAsync(&ws, pl.workspace_bytes, s));
+    p.part_mean = (double*)ws;
+    p.part_m2 = p.part_mean + (uint64_t)pl.splits * G;
+  }
+  hipEvent_t ev_b = opts ? (hipEvent_t)opts->ev_begin : nullptr;
+  hipEvent_t ev_e = opts ? (hipEvent_t)opts->ev_end : nullptr;
+  hipError_t e = zmc::launch_scan(p, pl, desc->precision, s, ev_b, ev_e);
+  if (ws != nullptr) {
+    hipError_t e2 = hipFreeAsync(ws, s);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e != hipSuccess) return fail(ZMC_E_DEVICE, "scan launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+zmc_status zmc_scan_device(const zmc_scan_desc* desc, const double* d_axis_vals, double* d_f,
+                           double* d_sigma, void* stream) {
+  return zmc_scan_device_ex(desc, d_axis_vals, d_f, d_sigma, nullptr, stream);
+}
+
+zmc_status zmc_scan(const zmc_scan_desc* desc, double* f, double* sigma) {
+  uint64_t G = 0;
+  zmc_status st = validate(desc, &G);
+  if (st != ZMC_OK) return st;
+  if (desc->M > 0 && desc->axis_vals == nullptr) return fail(ZMC_E_INVALID, "axis_vals is NULL with M > 0");
+  if (f == nullptr || sigma == nullptr) return fail(ZMC_E_INVALID, "f or sigma is NULL");
+  uint64_t total = 0;
+  for (int l = 0; l < desc->M; ++l) total += (uint64_t)desc->axis_len[l];
+  double *d_axis = nullptr, *d_out = nullptr;
+  hipError_t e = hipSuccess;
+  if (total > 0) e = hipMalloc(&d_axis, total * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&d_out, 2 * G * sizeof(double));
+  if (e == hipSuccess && total > 0)
+    e = hipMemcpy(d_axis, desc->axis_vals, total * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(d_axis);
+    hipFree(d_out);
+    return fail(e == hipErrorOutOfMemory ? ZMC_E_NOMEM : ZMC_E_DEVICE, "staging failed: %s",
+                hipGetErrorString(e));
+  }
+  st = zmc_scan_device(desc, d_axis, d_out, d_out + G, nullptr);
+  if (st == ZMC_OK) {
+    e = hipMemcpy(f, d_out, G * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(sigma, d_out + G, G * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) st = fail(ZMC_E_DEVICE, "copy back failed: %s", hipGetErrorString(e));
+  }
+  hipFree(d_axis);
+  hipFree(d_out);
+  return st == ZMC_OK ? ok() : st;
+}
+
+zmc_status zmc_debug_words(uint64_t seed, uint64_t g, uint64_t w0, int64_t count, uint32_t* d_out,
+                           void* stream) {
+  if (count < 0 || (count > 0 && d_out == nullptr)) return fail(ZMC_E_INVALID, "bad output");
+  if (count > ((int64_t)1 << 38)) return fail(ZMC_E_INVALID, "count too large");
+  hipError_t e = zmc::launch_debug_words(seed, g, w0, count, d_out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(ZMC_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+zmc_status zmc_debug_values(const zmc_scan_desc* desc, const double* d_axis_vals, uint64_t g,
+                            uint64_t s0, int64_t count, double* d_out, void* stream) {
+  uint64_t G = 0;
+  zmc_status st = validate(desc, &G);
+  if (st != ZMC_OK) return st;
+  if (g >= G) return fail(ZMC_E_INVALID, "g = %llu >= G", (unsigned long long)g);
+  if (desc->M > 0 && d_axis_vals == nullptr) return fail(ZMC_E_INVALID, "d_axis_vals is NULL with M > 0");
+  if (count < 0 || (count > 0 && d_out == nullptr)) return fail(ZMC_E_INVALID, "bad output");
+  if (count > ((int64_t)1 << 38)) return fail(ZMC_E_INVALID, "count too large");
+  zmc_launch_opts o{ZMC_MODE_POINT_MAJOR, 256, 1, 1, nullptr, nullptr};
+  zmc::Plan pl;
+  st = make_plan(desc, G, &o, &pl);
+  if (st != ZMC_OK) return st;
+  zmc::ScanParams p;
+  fill_params(desc, G, pl, d_axis_vals, nullptr, nullptr, &p);
+  hipError_t e = zmc::launch_debug_values(p, desc->precision, g, s0, count, d_out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(ZMC_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+}  // extern "C"

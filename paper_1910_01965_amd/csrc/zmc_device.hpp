@@ -1,0 +1,396 @@
+// zmc_device.hpp -- device building blocks of the parameter-scan kernels
+// (gfx950, wave64): the counter-based generator, the uniform maps, the
+// integrand families, per-lane accumulators and the FP64 merges.
+//
+// Method: direct Monte Carlo at every grid point (ZMCintegral-v5, Sec. 2,
+// Eq. (1)); the paper leaves the generator, the sample layout and the error
+// estimate open, and the library fixes them as stated in include/zmc.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace zmc {
+
+constexpr int kMaxParams = 16;
+constexpr int kMaxDims = 8;
+
+// Everything a scan kernel needs, passed by value as the kernel argument.
+struct ScanParams {
+  uint64_t G;            // grid points
+  uint64_t n;            // samples per point
+  uint64_t n_groups;     // ceil(n / 4)
+  uint64_t gps;          // groups per split
+  uint64_t seed;
+  uint64_t point_blocks; // ceil(G / block) (point-major)
+  int32_t M, N, splits, family;
+  int64_t axis_len[kMaxParams];
+  int64_t axis_off[kMaxParams];
+  uint64_t axis_stride[kMaxParams];  // prod of the lengths of later axes
+  double lo[kMaxDims], hi[kMaxDims];
+  double vol;
+  const double* axis;    // device: concatenated value lists
+  double* f;             // device outputs [G]
+  double* sigma;
+  double* part_mean;     // device split partials [splits][G] (or null)
+  double* part_m2;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  A round takes the high
+// and low halves of the products of words 0 and 2 with the two multipliers
+// and mixes the highs with words 1, 3 and the round key; the key advances by
+// the two Weyl increments.  On gfx950 a 32x32->64 product is one full-rate
+// v_mad_u64_u32 and the three-way xor is one v_bitop3_b32 (truth table 0x96).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+struct Words4 {
+  uint32_t r[4];
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+    const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+  }
+  Words4 w;
+  w.r[0] = c0; w.r[1] = c1; w.r[2] = c2; w.r[3] = c3;
+  return w;
+}
+
+// Block b of grid point g: counter (b lo, b hi, g lo, g hi), key = seed.
+__device__ __forceinline__ Words4 philox_block(uint64_t b, uint64_t g, uint64_t seed) {
+  return philox4x32_10((uint32_t)b, (uint32_t)(b >> 32), (uint32_t)g, (uint32_t)(g >> 32),
+                       (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// ---------------------------------------------------------------------------
+// Uniform variates.  The per-dimension affine map y = A t + B is folded into
+// each family; t is
+//   FP64: u = (r + 1/2) 2^-32 exactly, A = hi - lo, B = lo (y = fma(A, u, B));
+//   FP32: v = 1 + (r >> 9) 2^-23 in [1, 2) built from the bits (one
+//         v_alignbit_b32), A = hi - lo, B = lo - A (1 - 2^-24), so that
+//         A v + B = lo + A ((r >> 9) + 1/2) 2^-23.
+// ---------------------------------------------------------------------------
+template <typename T> struct Unif;
+
+template <> struct Unif<double> {
+  static __device__ __forceinline__ double t(uint32_t r) {
+    return ((double)r + 0.5) * 0x1p-32;
+  }
+  static constexpr double center = 0.5;
+  static __host__ __device__ inline void affine(double lo, double hi, double* A, double* B) {
+    *A = hi - lo;
+    *B = lo;
+  }
+};
+
+template <> struct Unif<float> {
+  static __device__ __forceinline__ float t(uint32_t r) {
+    // (0x7F : r) >> 9 = 0x3F800000 | (r >> 9): a float in [1, 2)
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, r, 9u));
+  }
+  static constexpr float center = 1.5f;
+  static __host__ __device__ inline void affine(double lo, double hi, double* A, double* B) {
+    *A = hi - lo;
+    *B = lo - (hi - lo) * (1.0 - 0x1p-24);
+  }
+};
+
+template <typename T> __device__ __forceinline__ T fmaT(T a, T b, T c);
+template <> __device__ __forceinline__ double fmaT(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+template <> __device__ __forceinline__ float fmaT(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
+constexpr double kLog2e = 1.4426950408889634074;
+
+// Parameter x_l of grid point g (C order: stride_l = prod_{j>l} L_j).
+__device__ __forceinline__ double param_x(const ScanParams& p, uint64_t g, int l) {
+  const uint64_t i = (g / p.axis_stride[l]) % (uint64_t)p.axis_len[l];
+  return p.axis[p.axis_off[l] + (int64_t)i];
+}
+
+// ---------------------------------------------------------------------------
+// Integrand families.  Each one holds the per-point constants (set up once
+// per point in FP64, then rounded to T) and evaluates one sample from its N
+// variates t[0..N-1].
+// ---------------------------------------------------------------------------
+
+// sin(sum_l x_l + sum_k y_k): the paper's test integrand, Eq. (2) and Eq. (4).
+template <typename T, int N> struct SinSum {
+  static constexpr int kMinDims = 1;
+  T A[N], B[N];
+  T sx;        // FP64: sum of x; FP32: sum x + sum B folded in
+  __device__ void setup(const ScanParams& p, uint64_t g) {
+    double s = 0.0, sb = 0.0;
+    for (int l = 0; l < p.M; ++l) s += param_x(p, g, l);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double a, b;
+      Unif<T>::affine(p.lo[k], p.hi[k], &a, &b);
+      A[k] = (T)a;
+      B[k] = (T)b;
+      sb += b;
+    }
+    sx = sizeof(T) == 8 ? (T)s : (T)(s + sb);
+  }
+  __device__ __forceinline__ T value(const T* t) const {
+    if constexpr (sizeof(T) == 8) {
+      double sy = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) sy += fmaT(A[k], t[k], B[k]);
+      return sin(sx + sy);
+    } else {
+      float ph = sx;
+#pragma unroll
+      for (int k = 0; k < N; ++k) ph = fmaT(A[k], t[k], ph);
+      return sinf(ph);
+    }
+  }
+};
+
+// exp(-(sum_{k<=M} x_k y_k^2 + sum_{k>M} y_k^2)).
+template <typename T, int N> struct Gauss {
+  static constexpr int kMinDims = 1;
+  T A[N], B[N], c[N];   // FP32: c carries log2(e) for exp2
+  __device__ void setup(const ScanParams& p, uint64_t g) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double a, b;
+      Unif<T>::affine(p.lo[k], p.hi[k], &a, &b);
+      A[k] = (T)a;
+      B[k] = (T)b;
+      const double x = (k < p.M) ? param_x(p, g, k) : 1.0;
+      c[k] = sizeof(T) == 8 ? (T)x : (T)(x * kLog2e);
+    }
+  }
+  __device__ __forceinline__ T value(const T* t) const {
+    T q = (T)0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const T y = fmaT(A[k], t[k], B[k]);
+      q = fmaT(c[k] * y, y, q);
+    }
+    if constexpr (sizeof(T) == 8) {
+      return exp(-q);
+    } else {
+      return __builtin_amdgcn_exp2f(-q);
+    }
+  }
+};
+
+// cos(x1 y1 + x2 y2 + sum_{k>=3} y_k) exp(-x3^2 y1 y2) + x4.
+template <typename T, int N> struct CosExp {
+  static constexpr int kMinDims = 2;
+  T A[N], B[N];
+  T x1, x2, nx3sq, x4;  // nx3sq = -x3^2 (FP32: times log2(e))
+  T rest;               // FP32: sum of B_k for k >= 3, folded into the phase
+  __device__ void setup(const ScanParams& p, uint64_t g) {
+    double sb = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double a, b;
+      Unif<T>::affine(p.lo[k], p.hi[k], &a, &b);
+      A[k] = (T)a;
+      B[k] = (T)b;
+      if (k >= 2) sb += b;
+    }
+    x1 = (T)param_x(p, g, 0);
+    x2 = (T)param_x(p, g, 1);
+    const double x3 = param_x(p, g, 2);
+    nx3sq = sizeof(T) == 8 ? (T)(-(x3 * x3)) : (T)(-(x3 * x3) * kLog2e);
+    x4 = (T)param_x(p, g, 3);
+    rest = (T)sb;
+  }
+  __device__ __forceinline__ T value(const T* t) const {
+    const T y1 = fmaT(A[0], t[0], B[0]);
+    const T y2 = fmaT(A[1], t[1], B[1]);
+    if constexpr (sizeof(T) == 8) {
+      double ph = x1 * y1 + x2 * y2;
+#pragma unroll
+      for (int k = 2; k < N; ++k) ph += fmaT(A[k], t[k], B[k]);
+      return cos(ph) * exp(nx3sq * y1 * y2) + x4;
+    } else {
+      float ph = rest;
+#pragma unroll
+      for (int k = 2; k < N; ++k) ph = fmaT(A[k], t[k], ph);
+      ph = fmaT(x1, y1, fmaT(x2, y2, ph));
+      const float e = __builtin_amdgcn_exp2f(nx3sq * y1 * y2);
+      return fmaT(cosf(ph), e, x4);
+    }
+  }
+};
+
+// 1: the sampler must reproduce the box volume exactly.
+template <typename T, int N> struct Const {
+  static constexpr int kMinDims = 1;
+  __device__ void setup(const ScanParams&, uint64_t) {}
+  __device__ __forceinline__ T value(const T*) const { return (T)1; }
+};
+
+// sum_k y_k.
+template <typename T, int N> struct Linear {
+  static constexpr int kMinDims = 1;
+  T A[N], B[N];
+  __device__ void setup(const ScanParams& p, uint64_t) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double a, b;
+      Unif<T>::affine(p.lo[k], p.hi[k], &a, &b);
+      A[k] = (T)a;
+      B[k] = (T)b;
+    }
+  }
+  __device__ __forceinline__ T value(const T* t) const {
+    T s = (T)0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) s += fmaT(A[k], t[k], B[k]);
+    return s;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// One group of four consecutive samples s = 4j .. 4j+3 of point g uses the N
+// Philox blocks b = jN .. jN+N-1 (words 4Nj .. 4Nj+4N-1, word i of the group
+// being coordinate i mod N of sample 4j + i / N).
+// ---------------------------------------------------------------------------
+template <class Fam, typename T, int N>
+__device__ __forceinline__ void eval_group(const Fam& fam, uint64_t j, uint64_t g,
+                                           uint64_t seed, T v[4]) {
+  T t[4 * N];
+  const uint64_t b0 = j * (uint64_t)N;
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    const Words4 w = philox_block(b0 + c, g, seed);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[4 * c + i] = Unif<T>::t(w.r[i]);
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) v[s] = fam.value(t + s * N);
+}
+
+// ---------------------------------------------------------------------------
+// Per-lane accumulation: shifted sums of d = v - c and d^2 in T, each with a
+// Kahan compensation term, four samples at a time.  c is the integrand at the
+// box centre, which keeps the final M2 = S2 - S1^2 / n well conditioned.
+// ---------------------------------------------------------------------------
+template <typename T> struct LaneAcc {
+  T c;
+  T s1, e1, s2, e2;
+  __device__ __forceinline__ void init(T shift) {
+    c = shift;
+    s1 = e1 = s2 = e2 = (T)0;
+  }
+  __device__ __forceinline__ static void kahan(T& s, T& e, T x) {
+    const T y = x - e;
+    const T tt = s + y;
+    e = (tt - s) - y;
+    s = tt;
+  }
+  __device__ __forceinline__ void add4(const T v[4]) {
+    const T d0 = v[0] - c, d1 = v[1] - c, d2 = v[2] - c, d3 = v[3] - c;
+    const T s = (d0 + d1) + (d2 + d3);
+    const T q = fmaT(d0, d0, d1 * d1) + fmaT(d2, d2, d3 * d3);
+    kahan(s1, e1, s);
+    kahan(s2, e2, q);
+  }
+  // the first `valid` of the four values count (ragged last group)
+  __device__ __forceinline__ void add_partial(const T v[4], int valid) {
+    T w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = (i < valid) ? v[i] : c;
+    add4(w);
+  }
+};
+
+// Welford state (count, mean, M2) in FP64.
+struct Moments {
+  double n, mean, m2;
+};
+
+template <typename T>
+__device__ __forceinline__ Moments to_moments(const LaneAcc<T>& a, double count) {
+  Moments m;
+  m.n = count;
+  if (count > 0.0) {
+    const double S1 = (double)a.s1 - (double)a.e1;
+    const double S2 = (double)a.s2 - (double)a.e2;
+    m.mean = (double)a.c + S1 / count;
+    m.m2 = S2 - S1 * (S1 / count);
+    if (m.m2 < 0.0) m.m2 = 0.0;
+  } else {
+    m.mean = 0.0;
+    m.m2 = 0.0;
+  }
+  return m;
+}
+
+// Chan, Golub, LeVeque pairwise merge; `a` is always the lower-indexed part
+// so that every merge order is fixed.
+__device__ __forceinline__ Moments merge(const Moments& a, const Moments& b) {
+  if (b.n == 0.0) return a;
+  if (a.n == 0.0) return b;
+  Moments m;
+  m.n = a.n + b.n;
+  const double d = b.mean - a.mean;
+  const double wb = b.n / m.n;
+  m.mean = a.mean + d * wb;
+  m.m2 = a.m2 + b.m2 + d * d * a.n * wb;
+  return m;
+}
+
+// Butterfly over the 64 lanes; every lane ends with the merge of all 64,
+// combined in lane order at every level.
+__device__ __forceinline__ Moments wave_merge(Moments m) {
+  const int lane = (int)(threadIdx.x & 63u);
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    Moments o;
+    o.n = __shfl_xor(m.n, off, 64);
+    o.mean = __shfl_xor(m.mean, off, 64);
+    o.m2 = __shfl_xor(m.m2, off, 64);
+    m = (lane & off) ? merge(o, m) : merge(m, o);
+  }
+  return m;
+}
+
+// Samples in split sp (groups [sp*gps, min((sp+1)*gps, n_groups)), the last
+// group of the scan possibly short).
+__host__ __device__ __forceinline__ uint64_t split_samples(uint64_t n, uint64_t n_groups,
+                                                           uint64_t gps, uint64_t sp) {
+  const uint64_t j0 = sp * gps;
+  uint64_t j1 = j0 + gps;
+  if (j1 > n_groups) j1 = n_groups;
+  if (j0 >= j1) return 0;
+  uint64_t s1 = 4 * j1;
+  if (s1 > n) s1 = n;
+  return s1 - 4 * j0;
+}
+
+__device__ __forceinline__ void finalize(const ScanParams& p, uint64_t g, const Moments& m) {
+  p.f[g] = p.vol * m.mean;
+  p.sigma[g] = p.vol * sqrt(m.m2 / (m.n * (m.n - 1.0)));
+}
+
+}  // namespace zmc

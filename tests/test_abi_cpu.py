@@ -1,0 +1,120 @@
+"""The C ABI on the CPU: the library loads, exports every declared symbol,
+validates descriptors and plans work without touching a device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1910_01965_amd import zmc
+from paper_1910_01965_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "zmc.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(zmc_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(zmc.LIB_PATH):
+        pytest.fail("libzmc.so is not built (run __graft_entry__.build())")
+    return zmc.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(zmc.EXPORTS) == set(names)
+
+
+def test_version(lib):
+    assert lib.zmc_version().decode().startswith("zmc")
+
+
+GOOD = wl.ScanSpec("gauss", [np.linspace(0.1, 10, 5), np.linspace(0.1, 10, 7)],
+                   np.zeros(3), np.ones(3), 64, 1, "fp32")
+
+
+@pytest.mark.parametrize("bad,status", [
+    (GOOD.with_(samples=1), 1),
+    (GOOD.with_(samples=0), 1),
+    (GOOD.with_(lo=np.array([0.0, 1.0, 0.0])), 1),            # lo >= hi
+    (GOOD.with_(hi=np.array([1.0, np.nan, 1.0])), 1),
+    (GOOD.with_(lo=np.array([-np.inf, 0.0, 0.0])), 1),
+    (GOOD.with_(family="cosexp"), 1),                          # needs M = 4
+    (GOOD.with_(axes=[np.arange(1.0, 3.0)] * 4), 1),           # GAUSS needs M <= N
+    (GOOD.with_(family="nope"), 1),
+    (GOOD.with_(precision="fp16"), 1),
+    (GOOD.with_(axes=[np.arange(2.0)] * 17), 1),               # M > 16
+    (GOOD.with_(lo=np.zeros(17), hi=np.ones(17)), 1),          # N > 16
+    (GOOD.with_(lo=np.zeros(12), hi=np.ones(12)), 4),          # N 9..16: unsupported
+    (GOOD.with_(axes=[np.arange(1 << 21, dtype=np.float64)] * 3, family="sin_sum"), 1),  # G > 2^62
+])
+def test_invalid_descriptors(lib, bad, status):
+    with pytest.raises(zmc.ZmcError) as ei:
+        zmc.validate(bad)
+    assert ei.value.status == status
+    assert lib.zmc_last_error().decode() != ""
+
+
+def test_valid_descriptors(lib):
+    assert zmc.validate(GOOD) == 35
+    assert zmc.validate(wl.ScanSpec("sin_sum", [], np.zeros(2), np.ones(2), 2, 0)) == 1
+    assert zmc.validate(wl.plain_fp64()) == 1000
+    assert zmc.validate(wl.gauss_2p()) == 10**6
+    assert zmc.validate(wl.cosexp_4p()) == 10**8
+    assert lib.zmc_last_error().decode() == ""
+
+
+def test_null_descriptor_and_outputs(lib):
+    assert lib.zmc_validate(None, None) == 1
+    d = zmc.Desc(GOOD)
+    assert lib.zmc_scan(d.ref, None, None) == 1
+    assert lib.zmc_scan_device(d.ref, None, None, None, None) == 1
+    assert lib.zmc_debug_words(0, 0, 0, -1, None, None) == 1
+    assert lib.zmc_debug_words(0, 0, 0, 4, None, None) == 1
+
+
+def _covers(p):
+    # the pieces cover every group exactly once, none empty
+    assert p["splits"] >= 1
+    assert p["splits"] * p["groups_per_split"] >= p["groups"]
+    assert (p["splits"] - 1) * p["groups_per_split"] < p["groups"]
+
+
+@pytest.mark.parametrize("spec", [wl.plain_fp64(), wl.gauss_2p(), wl.cosexp_4p(),
+                                  wl.plain_fp64(points=3, samples=7),
+                                  wl.gauss_2p(points_per_axis=9, samples=4097)])
+def test_plans_cover_all_work(lib, spec):
+    for mode in ("auto", "point_major", "sample_major"):
+        for splits in (None, 1, 3, 1000):
+            p = zmc.plan(spec, mode=mode, splits=splits, cu_count=256)
+            _covers(p)
+            assert p["grid_points"] == spec.G
+            assert p["groups"] == (spec.samples + 3) // 4
+            if p["splits"] > 1:
+                assert p["workspace_bytes"] == 16 * p["splits"] * spec.G
+            else:
+                assert p["workspace_bytes"] == 0
+
+
+def test_auto_plans_for_the_workloads(lib):
+    p0 = zmc.plan(wl.plain_fp64(), cu_count=256)
+    assert p0["mode"] == "sample_major"
+    p1 = zmc.plan(wl.gauss_2p(), cu_count=256)
+    assert p1["mode"] == "point_major" and p1["splits"] > 1
+    p2 = zmc.plan(wl.cosexp_4p(), cu_count=256)
+    assert p2["mode"] == "point_major" and p2["splits"] == 1 and p2["blocks"] == 390625
+
+
+def test_bad_launch_options(lib):
+    for kw in ({"block": 100}, {"block": 2048}, {"mode": "point_major", "block": 512}):
+        with pytest.raises(zmc.ZmcError):
+            zmc.plan(GOOD, cu_count=256, **kw)

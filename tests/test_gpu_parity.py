@@ -1,0 +1,236 @@
+"""GPU library vs the oracle, through the C ABI (needs an MI355X).
+
+FP64 path: |f - f_ref| and |sigma - sigma_ref| within 1e-12 of their scales
+(tests/parity.py); FP32-evaluation path: 2e-5 on f, 1e-3 on sigma.  Sizes
+range from tiny ragged cases to the full 1e6- and 1e8-point grids, where the
+oracle checks sampled points one by one.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as zo
+from paper_1910_01965_amd import workloads as wl
+
+import closed_forms as cf
+import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_01965_amd import zmc
+    zmc.load()  # raises when the HIP library is missing: no fallback
+    return torch
+
+
+def _zmc():
+    from paper_1910_01965_amd import zmc
+    return zmc
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(spec, **kw):
+    import torch
+    f, s = _zmc().scan(spec, **kw)
+    torch.cuda.synchronize()
+    return f.cpu().numpy(), s.cpu().numpy()
+
+
+# ---------------------------------------------------------------- words ----
+@pytest.mark.parametrize("seed,g,w0,count", [
+    (42, 0, 0, 4096),
+    (42, 999, 1, 1000),
+    (0xDEADBEEFCAFEF00D, (1 << 33) + 17, 12, 333),
+    (1, 3, (1 << 34) + 8, 64),
+    (0xFFFFFFFFFFFFFFFF, (1 << 64) - 1, 4 * ((1 << 32) - 1), 64),
+])
+def test_device_words_match_oracle(seed, g, w0, count):
+    _say(f"words seed={seed} g={g} w0={w0} count={count}")
+    got = _zmc().debug_words(seed, g, w0, count).cpu().numpy()
+    ref = np.array([zo.word(seed, g, w0 + i) for i in range(count)], dtype=np.int64)
+    assert np.array_equal(got, ref)
+
+
+# --------------------------------------------------------------- values ----
+def _family_specs(precision):
+    out = []
+    for N in range(1, 9):
+        out.append(wl.ScanSpec("sin_sum", [np.linspace(0, 1, 5)], np.zeros(N), np.linspace(1, 2, N),
+                               64, 7, precision))
+        M = min(2, N)
+        out.append(wl.ScanSpec("gauss", [np.linspace(0.1, 10, 3)] * M, -0.5 * np.ones(N),
+                               np.linspace(1, 2, N), 64, 8, precision))
+        if N >= 2:
+            hi = np.ones(N)
+            hi[0] = 2.0
+            out.append(wl.ScanSpec("cosexp", [np.linspace(-1, 1, 3)] * 4, np.zeros(N), hi, 64, 9,
+                                   precision))
+        out.append(wl.ScanSpec("linear", [np.arange(3.0)], -np.ones(N), np.linspace(0.5, 3, N), 64,
+                               10, precision))
+        out.append(wl.ScanSpec("const", [np.arange(2.0)], np.zeros(N), np.ones(N), 64, 11, precision))
+    return out
+
+
+@pytest.mark.parametrize("spec", _family_specs("fp64"), ids=lambda s: f"{s.family}-N{s.N}")
+def test_device_values_fp64_match_oracle(spec):
+    _say(f"values fp64 {spec.family} N={spec.N}")
+    for g in (0, spec.G - 1):
+        got = _zmc().debug_values(spec, g, 3, 61).cpu().numpy()
+        ref = zo.values(spec, g, 3, 61)
+        assert np.allclose(got, ref, rtol=1e-14, atol=1e-15), (g, np.max(np.abs(got - ref)))
+
+
+@pytest.mark.parametrize("spec", _family_specs("fp32"), ids=lambda s: f"{s.family}-N{s.N}")
+def test_device_values_fp32_close_to_oracle(spec):
+    _say(f"values fp32 {spec.family} N={spec.N}")
+    for g in (0, spec.G - 1):
+        got = _zmc().debug_values(spec, g, 0, 64).cpu().numpy()
+        ref = zo.values(spec, g, 0, 64)
+        scale = 1.0 + np.abs(ref)
+        assert np.all(np.abs(got - ref) <= 4e-6 * scale * spec.N), (g, np.max(np.abs(got - ref)))
+
+
+# ------------------------------------------------------- whole scans -------
+def test_plain_fp64_full_grid():
+    spec = wl.plain_fp64()
+    _say(f"scan {spec.name}")
+    f, s = _run(spec)
+    f_ref, s_ref = zo.scan(spec)
+    _, _, msg = parity.check(f, s, f_ref, s_ref, spec.samples, "fp64", spec.name)
+    _say(msg)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_gauss_reduced_grid(precision):
+    spec = wl.gauss_2p(points_per_axis=40, samples=1 << 14, precision=precision)
+    _say(f"scan {spec.name} {precision}")
+    f, s = _run(spec)
+    f_ref, s_ref = zo.scan(spec)
+    _, _, msg = parity.check(f, s, f_ref, s_ref, spec.samples, precision, spec.name)
+    _say(msg)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_cosexp_reduced_grid(precision):
+    spec = wl.cosexp_4p(points_per_axis=7, samples=4096, precision=precision)
+    _say(f"scan {spec.name} {precision}")
+    f, s = _run(spec)
+    f_ref, s_ref = zo.scan(spec)
+    _, _, msg = parity.check(f, s, f_ref, s_ref, spec.samples, precision, spec.name)
+    _say(msg)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_gauss_full_grid_sampled(precision):
+    spec = wl.gauss_2p(precision=precision)
+    _say(f"scan {spec.name} full grid {precision}")
+    f, s = _run(spec)
+    idx = np.sort(np.random.default_rng(1).choice(spec.G, 300, replace=False))
+    idx = np.concatenate([[0, spec.G - 1], idx]).astype(np.uint64)
+    f_ref, s_ref = zo.scan(spec, idx)
+    ii = idx.astype(np.int64)
+    _, _, msg = parity.check(f[ii], s[ii], f_ref, s_ref, spec.samples, precision, spec.name)
+    _say(msg)
+    # at any size: every point against the exact integral and standard error
+    f_true, var = cf.gauss_exact(spec)
+    ok, cmsg = cf.coverage_ok((f - f_true) / np.sqrt(var / spec.samples), spec.name)
+    ratio = s / np.sqrt(var / spec.samples)
+    assert abs(np.median(ratio) - 1.0) < 0.01, np.median(ratio)
+    _say(cmsg)
+    assert ok, cmsg
+
+
+def test_cosexp_full_grid_subsample():
+    spec = wl.cosexp_4p(precision="fp32")
+    _say(f"scan {spec.name} full grid fp32")
+    import torch
+    f, s = _zmc().scan(spec)
+    idx = wl.cosexp_subsample()
+    ti = torch.from_numpy(idx.astype(np.int64)).cuda()
+    fs, ss = f[ti].cpu().numpy(), s[ti].cpu().numpy()
+    assert bool(torch.isfinite(f).all()) and bool(torch.isfinite(s).all())
+    del f, s
+    f_ref, s_ref = zo.scan(spec, idx)
+    _, _, msg = parity.check(fs, ss, f_ref, s_ref, spec.samples, "fp32", spec.name + " subsample")
+    _say(msg)
+
+
+# --------------------------------------------- decomposition, edge cases ----
+DECOMPOSITIONS = [
+    dict(mode="point_major", splits=1), dict(mode="point_major", splits=3),
+    dict(mode="point_major", block=64, splits=7), dict(mode="sample_major", splits=1),
+    dict(mode="sample_major", block=64, splits=2), dict(mode="sample_major", block=1024, splits=5),
+    dict(),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_decomposition_invariance(precision):
+    spec = wl.gauss_2p(points_per_axis=19, samples=4099, precision=precision)
+    f_ref, s_ref = zo.scan(spec)
+    outs = []
+    for kw in DECOMPOSITIONS:
+        _say(f"decomposition {kw} {precision}")
+        f, s = _run(spec, **kw)
+        parity.check(f, s, f_ref, s_ref, spec.samples, precision, f"{kw}")
+        outs.append((f, s))
+    tol = 1e-13 if precision == "fp64" else 2e-6
+    for f, s in outs[1:]:
+        assert np.allclose(f, outs[0][0], rtol=tol, atol=tol * np.abs(outs[0][0]).max())
+
+
+def test_repeatable_bitwise():
+    for precision in ("fp64", "fp32"):
+        spec = wl.gauss_2p(points_per_axis=300, samples=1024, precision=precision)
+        _say(f"repeat {spec.name}")
+        a = _run(spec)
+        b = _run(spec)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+EDGE = [
+    wl.ScanSpec("sin_sum", [], np.zeros(3), np.ones(3), 1001, 5),            # M = 0, G = 1
+    wl.ScanSpec("sin_sum", [np.linspace(0, 1, 7)], np.zeros(1), np.ones(1), 2, 5),
+    wl.ScanSpec("sin_sum", [np.linspace(0, 1, 7)], np.zeros(2), np.ones(2), 3, 5),
+    wl.ScanSpec("gauss", [np.linspace(0.1, 9, 300)], np.zeros(8), np.ones(8), 5, 6),
+    wl.ScanSpec("cosexp", [np.linspace(-1, 1, 3)] * 4, np.zeros(5), np.array([2.0, 1, 1, 1, 1]), 1001, 7),
+    wl.ScanSpec("linear", [np.arange(257.0)], -np.ones(7), np.ones(7), 4097, 8),
+    wl.ScanSpec("gauss", [np.linspace(0.1, 9, 70000)], np.zeros(2), np.ones(2), 33, 9),
+]
+
+
+@pytest.mark.parametrize("spec", EDGE, ids=lambda s: f"{s.family}-G{s.G}-N{s.N}-n{s.samples}")
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["auto", "point_major", "sample_major"])
+def test_edge_shapes(spec, precision, mode):
+    spec = spec.with_(precision=precision)
+    _say(f"edge {spec.family} G={spec.G} N={spec.N} n={spec.samples} {precision} {mode}")
+    f, s = _run(spec, mode=mode)
+    f_ref, s_ref = zo.scan(spec)
+    parity.check(f, s, f_ref, s_ref, spec.samples, precision, f"edge {mode}")
+
+
+def test_const_is_exact_volume_on_gpu():
+    for precision in ("fp64", "fp32"):
+        spec = wl.ScanSpec("const", [np.arange(5.0)], np.array([-1.0, 0.5]), np.array([2.0, 1.75]),
+                           999, 1, precision)
+        f, s = _run(spec)
+        assert np.all(f == 3.0 * 1.25) and np.all(s == 0.0)
+
+
+def test_host_entry_point_matches_device():
+    spec = wl.gauss_2p(points_per_axis=33, samples=2048, precision="fp32")
+    _say("host entry point")
+    fd, sd = _run(spec)
+    fh, sh = _zmc().scan_host(spec)
+    assert np.array_equal(fd, fh) and np.array_equal(sd, sh)
