@@ -26,30 +26,24 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MC samples/s & grid pts/s on 1 MI355X (fp32 vs fp64); p50/p99 scan latency"
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes per clock at 2.4 GHz = one 32-bit VALU
-# lane-operation slot per lane per clock (the FP32 vector peak of 157.3
-# TFLOP/s counts a packed FMA as 4 FLOP in one such slot).
-VALU_PEAK = 256 * 64 * 2.4e9
+# MI355X VALU peak in 32-bit lane-operations: 256 CUs x 128 lanes per clock
+# x 2.4 GHz = 7.864e13/s, i.e. the published FP32 vector peak of 157.3 TFLOP/s
+# with an FMA counted as one operation (2 FLOP).  On gfx950 the two-operand
+# (VOP2) ALU forms issue at that rate; three-operand (VOP3) forms such as
+# v_mad_u64_u32 and v_bitop3_b32 at half of it; transcendentals at a quarter.
+VALU_PEAK = 256 * 128 * 2.4e9
 
 
-def valu_ops_per_sample(family, N, precision):
-    """Algorithmic VALU issue slots per sample (full-rate = 1, the measured
-    half-rate transcendentals = 2): Philox 2.5N rounds x (2 wide multiplies +
-    2 three-way xors), N conversions + N map FMAs, the integrand, and 8 for
-    the compensated accumulation."""
+def valu_ops_per_sample(family, N):
+    """Algorithmic 32-bit lane-operations per sample: Philox4x32-10 needs N/4
+    blocks per sample, i.e. 2.5N rounds x (2 wide multiplies + 2 three-way
+    xors); the uniform map N conversions + N FMAs; the integrand (GAUSS: N
+    mul + N FMA + 1 exp; SIN_SUM: N adds + 1 sin; COSEXP: 2 FMA + (N-2) adds
+    + 1 cos + 2 mul + 1 exp + 1 add); the compensated accumulation 8."""
     rng = 2.5 * N * 4
     mapping = 2 * N
-    if family == "gauss":
-        integrand = 2 * N + 2
-    elif family == "sin_sum":
-        integrand = N + 2
-    elif family == "cosexp":
-        integrand = 2 + (N - 2) + 2 + 2 + 2 + 1
-    else:
-        integrand = N
-    acc = 8
-    w = rng + mapping + integrand + acc
-    return float(w if precision == "fp32" else w)
+    integrand = {"gauss": 2 * N + 1, "sin_sum": N + 1, "cosexp": N + 5}.get(family, N)
+    return float(rng + mapping + integrand + 8)
 
 
 def log(*a):
@@ -106,7 +100,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=5)
-    ap.add_argument("--cpu-points", type=int, default=12000)
+    ap.add_argument("--cpu-points", type=int, default=48000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -137,10 +131,10 @@ def main():
     ms64 = r64["wall_s"] * 1e3 / args.fp64_steps
     log(f"fp64: {ms64:.3f} ms/step")
 
-    w = valu_ops_per_sample(spec.family, spec.N, "fp32")
+    w = valu_ops_per_sample(spec.family, spec.N)
     achieved = w * G * n / (kern_ms / 1e3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                "unit": "T lane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
                 "ops_per_sample": w, "kernel": "k_point_major<Gauss<float,3>>",
                 "kernel_ms": kern_ms}
 

@@ -185,6 +185,7 @@ void fill_params(const zmc_scan_desc* d, uint64_t G, const zmc::Plan& pl, const 
   p->N = d->N;
   p->splits = pl.splits;
   p->family = d->family;
+  p->fast_counter = (G <= ((uint64_t)1 << 32) && pl.groups * (uint64_t)d->N <= ((uint64_t)1 << 32)) ? 1 : 0;
   int64_t off = 0;
   uint64_t stride = 1;
   for (int l = d->M - 1; l >= 0; --l) {

@@ -24,6 +24,8 @@ struct ScanParams {
   uint64_t seed;
   uint64_t point_blocks; // ceil(G / block) (point-major)
   int32_t M, N, splits, family;
+  int32_t fast_counter;  // 1 when every word block b and grid index g is < 2^32
+  int32_t pad_;
   int64_t axis_len[kMaxParams];
   int64_t axis_off[kMaxParams];
   uint64_t axis_stride[kMaxParams];  // prod of the lengths of later axes
@@ -48,26 +50,36 @@ constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
 constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+__host__ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+#if defined(__HIP_DEVICE_COMPILE__)
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+  return a ^ b ^ c;
+#endif
 }
 
 struct Words4 {
   uint32_t r[4];
 };
 
-__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
-                                                uint32_t c3, uint32_t k0, uint32_t k1) {
+// One Philox round on (c0, c1, c2, c3) with round key (k0, k1).
+__host__ __device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                                      uint32_t& c3, uint32_t k0, uint32_t k1) {
+  const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+  const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+  const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+  const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+  c1 = (uint32_t)p1;
+  c3 = (uint32_t)p0;
+  c0 = n0;
+  c2 = n2;
+}
+
+__host__ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                         uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
-    const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
-    const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-    const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
-    const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
-    c1 = (uint32_t)p1;
-    c3 = (uint32_t)p0;
-    c0 = n0;
-    c2 = n2;
+    philox_round(c0, c1, c2, c3, k0, k1);
     k0 += kPhiloxW0;
     k1 += kPhiloxW1;
   }
@@ -77,9 +89,78 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
 }
 
 // Block b of grid point g: counter (b lo, b hi, g lo, g hi), key = seed.
-__device__ __forceinline__ Words4 philox_block(uint64_t b, uint64_t g, uint64_t seed) {
+__host__ __device__ __forceinline__ Words4 philox_block(uint64_t b, uint64_t g, uint64_t seed) {
   return philox4x32_10((uint32_t)b, (uint32_t)(b >> 32), (uint32_t)g, (uint32_t)(g >> 32),
                        (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// ---------------------------------------------------------------------------
+// The same blocks for the point-major layout when b < 2^32 and g < 2^32 (the
+// host checks both for the whole scan).  All lanes of a wave then share b and
+// differ in g only, so the first two rounds split into a per-lane part that
+// does not change from block to block (computed once per point) and a
+// wave-uniform part that the compiler keeps in scalar registers:
+//   round 1: (hi, lo)(M1 g) is per lane and fixed; (hi, lo)(M0 b) is uniform;
+//   round 2: M0 times the round-1 word 0 = hi(M1 g) ^ k0 is per lane and
+//            fixed; M1 times the round-1 word 2 = hi(M0 b) ^ k1 is uniform.
+// Only rounds 3..10 multiply per-lane, per-block values.
+// ---------------------------------------------------------------------------
+struct PhiloxLane {
+  uint32_t r1;   // round-1 output word 1: lo(M1 g)
+  uint32_t h2;   // hi(M0 * round-1 word 0)
+  uint32_t l2;   // lo(M0 * round-1 word 0)
+  uint32_t k0, k1;
+};
+
+__host__ __device__ __forceinline__ PhiloxLane philox_lane(uint32_t g, uint64_t seed) {
+  PhiloxLane L;
+  L.k0 = (uint32_t)seed;
+  L.k1 = (uint32_t)(seed >> 32);
+  const uint64_t p1 = (uint64_t)kPhiloxM1 * g;
+  const uint32_t w0 = (uint32_t)(p1 >> 32) ^ L.k0;  // counter word 1 (b hi) is 0
+  L.r1 = (uint32_t)p1;
+  const uint64_t p2 = (uint64_t)kPhiloxM0 * w0;
+  L.h2 = (uint32_t)(p2 >> 32);
+  L.l2 = (uint32_t)p2;
+  return L;
+}
+
+__host__ __device__ __forceinline__ Words4 philox_block_pm(uint32_t b, const PhiloxLane& L) {
+  // round 1 (key k): words 0, 1 per lane and fixed; words 2, 3 uniform
+  const uint64_t q0 = (uint64_t)kPhiloxM0 * b;
+  const uint32_t u2 = (uint32_t)(q0 >> 32) ^ L.k1;  // counter word 3 (g hi) is 0
+  const uint32_t u3 = (uint32_t)q0;
+  // round 2 (key k + W): the product with word 2 is uniform
+  const uint32_t k0b = L.k0 + kPhiloxW0, k1b = L.k1 + kPhiloxW1;
+  const uint64_t q1 = (uint64_t)kPhiloxM1 * u2;
+  uint32_t c0 = L.r1 ^ ((uint32_t)(q1 >> 32) ^ k0b);
+  uint32_t c1 = (uint32_t)q1;
+  uint32_t c2 = L.h2 ^ (u3 ^ k1b);
+  uint32_t c3 = L.l2;
+  uint32_t k0 = k0b + kPhiloxW0, k1 = k1b + kPhiloxW1;
+  {
+    // round 3: word 1 and the key are uniform, word 3 is per lane and fixed,
+    // so each new word is one per-lane product high half and one xor
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ (c1 ^ k0);
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+  }
+#pragma unroll
+  for (int round = 3; round < 10; ++round) {
+    philox_round(c0, c1, c2, c3, k0, k1);
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+  }
+  Words4 w;
+  w.r[0] = c0; w.r[1] = c1; w.r[2] = c2; w.r[3] = c3;
+  return w;
 }
 
 // ---------------------------------------------------------------------------
@@ -275,14 +356,27 @@ template <typename T, int N> struct Linear {
 // Philox blocks b = jN .. jN+N-1 (words 4Nj .. 4Nj+4N-1, word i of the group
 // being coordinate i mod N of sample 4j + i / N).
 // ---------------------------------------------------------------------------
-template <class Fam, typename T, int N>
-__device__ __forceinline__ void eval_group(const Fam& fam, uint64_t j, uint64_t g,
-                                           uint64_t seed, T v[4]) {
+// Word-block generators of one grid point: any counter, or the point-major
+// fast path (b < 2^32, g < 2^32, b shared by the wave).
+struct GenAny {
+  uint64_t g, seed;
+  __device__ __forceinline__ Words4 block(uint64_t b) const { return philox_block(b, g, seed); }
+};
+
+struct GenPointMajor {
+  PhiloxLane L;
+  __device__ __forceinline__ Words4 block(uint64_t b) const {
+    return philox_block_pm((uint32_t)b, L);
+  }
+};
+
+template <class Fam, typename T, int N, class Gen>
+__device__ __forceinline__ void eval_group(const Fam& fam, uint64_t j, const Gen& gen, T v[4]) {
   T t[4 * N];
   const uint64_t b0 = j * (uint64_t)N;
 #pragma unroll
   for (int c = 0; c < N; ++c) {
-    const Words4 w = philox_block(b0 + c, g, seed);
+    const Words4 w = gen.block(b0 + c);
 #pragma unroll
     for (int i = 0; i < 4; ++i) t[4 * c + i] = Unif<T>::t(w.r[i]);
   }

@@ -28,6 +28,24 @@ __device__ __forceinline__ T centre_value(const Fam& fam) {
   return fam.value(tc);
 }
 
+// Groups j0 .. jfull-1 in full, then (when `ragged`) the scan's short last
+// group; every lane of the wave walks the same j.
+template <class Fam, typename T, int N, class Gen>
+__device__ __forceinline__ void lane_groups(const Fam& fam, const Gen& gen, uint64_t j0,
+                                            uint64_t jfull, bool ragged, int tail,
+                                            LaneAcc<T>& acc) {
+  for (uint64_t j = j0; j < jfull; ++j) {
+    T v[4];
+    eval_group<Fam, T, N>(fam, j, gen, v);
+    acc.add4(v);
+  }
+  if (ragged) {
+    T v[4];
+    eval_group<Fam, T, N>(fam, jfull, gen, v);
+    acc.add_partial(v, tail);
+  }
+}
+
 template <class Fam, typename T, int N>
 __global__ __launch_bounds__(256) void k_point_major(ScanParams p) {
   const uint64_t sp = blockIdx.y;
@@ -35,6 +53,7 @@ __global__ __launch_bounds__(256) void k_point_major(ScanParams p) {
   const uint64_t j1 = (j0 + p.gps < p.n_groups) ? j0 + p.gps : p.n_groups;
   const bool ragged = (j1 == p.n_groups) && ((p.n & 3u) != 0);
   const uint64_t jfull = ragged ? j1 - 1 : j1;
+  const int tail = (int)(p.n - 4 * (p.n_groups - 1));
   const double count = (double)split_samples(p.n, p.n_groups, p.gps, sp);
   for (uint64_t pb = blockIdx.x; pb < p.point_blocks; pb += gridDim.x) {
     const uint64_t g = pb * blockDim.x + threadIdx.x;
@@ -43,15 +62,12 @@ __global__ __launch_bounds__(256) void k_point_major(ScanParams p) {
     fam.setup(p, g);
     LaneAcc<T> acc;
     acc.init(centre_value<Fam, T, N>(fam));
-    for (uint64_t j = j0; j < jfull; ++j) {
-      T v[4];
-      eval_group<Fam, T, N>(fam, j, g, p.seed, v);
-      acc.add4(v);
-    }
-    if (ragged) {
-      T v[4];
-      eval_group<Fam, T, N>(fam, j1 - 1, g, p.seed, v);
-      acc.add_partial(v, (int)(p.n - 4 * (j1 - 1)));
+    if (p.fast_counter) {
+      const GenPointMajor gen{philox_lane((uint32_t)g, p.seed)};
+      lane_groups<Fam, T, N>(fam, gen, j0, jfull, ragged, tail, acc);
+    } else {
+      const GenAny gen{g, p.seed};
+      lane_groups<Fam, T, N>(fam, gen, j0, jfull, ragged, tail, acc);
     }
     const Moments m = to_moments(acc, count);
     if (p.splits == 1) {
@@ -78,9 +94,10 @@ __global__ __launch_bounds__(1024) void k_sample_major(ScanParams p) {
     LaneAcc<T> acc;
     acc.init(centre_value<Fam, T, N>(fam));
     double count = 0.0;
+    const GenAny gen{g, p.seed};
     for (uint64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
       T v[4];
-      eval_group<Fam, T, N>(fam, j, g, p.seed, v);
+      eval_group<Fam, T, N>(fam, j, gen, v);
       if (j == last && tail != 4) {
         acc.add_partial(v, tail);
         count += (double)tail;
@@ -144,7 +161,7 @@ __global__ void k_debug_values(ScanParams p, uint64_t g, uint64_t s0, int64_t co
   Fam fam;
   fam.setup(p, g);
   T v[4];
-  eval_group<Fam, T, N>(fam, s >> 2, g, p.seed, v);
+  eval_group<Fam, T, N>(fam, s >> 2, GenAny{g, p.seed}, v);
   const unsigned k = (unsigned)(s & 3u);
   out[i] = (double)(k == 0 ? v[0] : k == 1 ? v[1] : k == 2 ? v[2] : v[3]);
 }
