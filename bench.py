@@ -33,6 +33,11 @@ METRIC = "MC samples/s & grid pts/s on 1 MI355X (fp32 vs fp64); p50/p99 scan lat
 # v_mad_u64_u32 and v_bitop3_b32 at half of it; transcendentals at a quarter.
 VALU_PEAK = 256 * 128 * 2.4e9
 
+# HBM bytes per dispatch of the main kernel on the default workload, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy (profiles/), keyed
+# by the library version they were taken with; null for any other build.
+TRAFFIC_BYTES = {"zmc 0.2 gfx950": 0.318e6 + 144.0e6}
+
 
 def valu_ops_per_sample(family, N):
     """Algorithmic 32-bit lane-operations per sample: Philox4x32-10 needs N/4
@@ -94,6 +99,18 @@ def cpu_baseline(spec, points, seed=0):
                       f"{dt:.1f} s"}
 
 
+def copy_probe(nbytes=1 << 30, reps=3):
+    """A plain device-to-device copy of known size: FETCH_SIZE / WRITE_SIZE
+    of its dispatches calibrate the HBM counters against nbytes."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,7 +119,12 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--cpu-points", type=int, default=48000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the scan shards by "
               "grid-point ranges across GPUs with no exchange, which this build does not run.",
@@ -133,8 +155,10 @@ def main():
 
     w = valu_ops_per_sample(spec.family, spec.N)
     achieved = w * G * n / (kern_ms / 1e3)
+    version = zmc.load().zmc_version().decode()
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                "unit": "T lane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                "unit": "T lane-op/s", "frac": achieved / VALU_PEAK,
+                "traffic": TRAFFIC_BYTES.get(version), "library": version,
                 "ops_per_sample": w, "kernel": "k_point_major<Gauss<float,3>>",
                 "kernel_ms": kern_ms}
 
