@@ -168,6 +168,149 @@ zmc_status zmc_debug_values(const zmc_scan_desc* desc, const double* d_axis_vals
                             uint64_t g, uint64_t s0, int64_t count, double* d_out,
                             void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched scans.  Many independent scans of uneven grid sizes, sample
+ * counts, families and dimensions run as one unit of work: the planner cuts
+ * every scan into tiles (256 grid points x one sample piece, or one point x
+ * one sample piece for grids below the tuned threshold), with tile shapes
+ * from the autotuned table (tune_table.txt next to the library, or
+ * $ZMC_TUNE_TABLE); one persistent kernel per (family, precision, N)
+ * variant drains its longest-first tile queue; a second pass merges split
+ * partials in split order.  The whole sequence is captured once in a
+ * hipGraph and replayed by zmc_batch_launch.  A scan's tiles depend only on
+ * the scan itself, so its results are bitwise the same alone and in any
+ * batch.  This generalises the paper's batches (Sec. 2, Fig. 1), where a
+ * grid is cut into pieces that each go to one GPU.
+ * ---------------------------------------------------------------------- */
+typedef struct zmc_batch zmc_batch;
+
+typedef struct zmc_batch_opts {
+  int32_t use_graph;          /* 1: capture and replay a hipGraph; 0: launch the
+                                 kernels directly on each zmc_batch_launch      */
+  int32_t parallel_variants;  /* 1: one graph branch per kernel variant (they may
+                                 overlap on the device); 0: one chain           */
+  int64_t pm_groups;          /* > 0: groups of four samples per lane in a
+                                 point-major tile (overrides the table)        */
+  int64_t sm_groups;          /* > 0: groups per sample-major tile (override)   */
+  int64_t pm_min_points;      /* > 0: smallest grid given point-major tiles     */
+  int32_t cu_count;           /* planner only: compute units (0 = device)       */
+  int32_t one_kernel;         /* 1: a single persistent kernel per precision runs
+                                 every family and N (one tile queue; register
+                                 use of the largest variant); 0: one kernel per
+                                 (family, precision, N) variant               */
+} zmc_batch_opts;
+
+typedef struct zmc_batch_info {
+  int32_t scans;              /* scans in the batch                            */
+  int32_t variants;           /* distinct (family, precision, N) kernels       */
+  int64_t tiles;              /* tiles over all scans                          */
+  uint64_t samples;           /* sum over scans of G * samples                 */
+  uint64_t points;            /* sum over scans of G                           */
+  uint64_t workspace_bytes;   /* device bytes of tables, staged lists, partials */
+  int32_t merge_scans;        /* scans with more than one sample piece         */
+  int32_t graph;              /* 1 when a hipGraph is replayed                 */
+} zmc_batch_info;
+
+/* Default options: use_graph = 1, parallel_variants = 1, table-driven tiles.
+ * Passing opts = NULL to the calls below means these defaults. */
+void zmc_batch_default_opts(zmc_batch_opts* opts);
+
+/* Host-only plan of a batch (validation, tiles, workspace), no device use
+ * when opts->cu_count > 0. */
+zmc_status zmc_batch_plan(const zmc_scan_desc* scans, int32_t n_scans,
+                          const zmc_batch_opts* opts, zmc_batch_info* info);
+
+/* Plans the batch, allocates its device tables and workspace, uploads them,
+ * and (use_graph) captures the graph, all on the current device.  d_f[i] and
+ * d_sigma[i] receive scan i's G doubles; d_axis_vals[i] holds its lists on
+ * the device (entries may be NULL when M = 0); when d_axis_vals itself is
+ * NULL the library stages scans[i].axis_vals into memory the batch owns.
+ * The descriptors are read only during this call; the device buffers must
+ * stay valid until zmc_batch_destroy.  Returns ZMC_E_INVALID (naming the
+ * scan) for any invalid descriptor. */
+zmc_status zmc_batch_create(const zmc_scan_desc* scans, int32_t n_scans,
+                            const double* const* d_axis_vals, double* const* d_f,
+                            double* const* d_sigma, const zmc_batch_opts* opts,
+                            zmc_batch** out);
+
+/* Enqueues the whole batch on `stream` (graph replay or direct launches).
+ * Calls on one batch must not overlap on the device: they share its
+ * counters and partials. */
+zmc_status zmc_batch_launch(zmc_batch* batch, void* stream);
+
+zmc_status zmc_batch_get_info(const zmc_batch* batch, zmc_batch_info* info);
+
+/* Frees the batch after waiting for its work to finish. */
+zmc_status zmc_batch_destroy(zmc_batch* batch);
+
+/* One-shot: create, launch on `stream`, wait for the stream, destroy. */
+zmc_status zmc_scan_batch(const zmc_scan_desc* scans, int32_t n_scans,
+                          const double* const* d_axis_vals, double* const* d_f,
+                          double* const* d_sigma, void* stream);
+
+/* Where the tile table came from: a file path or "built-in defaults". */
+const char* zmc_tune_source(void);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.  Scans are submitted
+ * one by one at any time; a scheduler thread admits them in arrival order
+ * while their device state (staged lists and split partials) fits the HBM
+ * budget and a slot is free, cuts each into the same tiles a batch would
+ * (so every result is bitwise the same alone, in a batch or in the mix),
+ * and runs short slices: each slice takes tiles round-robin from all
+ * admitted requests and runs them in one persistent kernel per precision,
+ * so requests that arrive while others are on the GPU join the next slice
+ * and their work overlaps on the device.  A request completes when its last
+ * tile and its split merge have run; its latency is completion minus submit
+ * time.  Requests that can never fit the budget fail with ZMC_E_NOMEM.
+ * ---------------------------------------------------------------------- */
+typedef struct zmc_server zmc_server;
+
+typedef struct zmc_server_opts {
+  uint64_t hbm_budget_bytes;   /* device-state budget of admitted requests
+                                  (0 = 64 GiB)                               */
+  int32_t max_slots;           /* admitted requests at once (0 = 256)        */
+  int32_t slice_tiles;         /* tiles per slice (0 = 4 per resident block) */
+  int32_t max_inflight;        /* slices enqueued ahead of the device (0 = 2) */
+  int32_t cu_count;            /* compute units (0 = device)                 */
+} zmc_server_opts;
+
+typedef struct zmc_server_stats {
+  uint64_t submitted, admitted, completed, failed;
+  uint64_t pending;            /* waiting for admission                      */
+  uint64_t active;             /* admitted, not yet complete                 */
+  uint64_t samples_completed;  /* sum of G * samples over completed requests */
+  uint64_t slices;             /* slices launched                            */
+  uint64_t tiles;              /* tiles launched                             */
+  uint64_t bytes_in_use;       /* device state held by admitted requests     */
+  uint64_t bytes_peak;
+} zmc_server_stats;
+
+/* Starts the scheduler thread on the current device. */
+zmc_status zmc_server_create(const zmc_server_opts* opts, zmc_server** out);
+
+/* Queues one scan; never waits for the GPU.  The descriptor and its host
+ * arrays are copied.  d_axis_vals may be NULL (the server stages
+ * desc->axis_vals); d_f and d_sigma (G doubles each) must stay valid until
+ * the request completes.  *ticket identifies the request. */
+zmc_status zmc_server_submit(zmc_server* server, const zmc_scan_desc* desc,
+                             const double* d_axis_vals, double* d_f, double* d_sigma,
+                             uint64_t* ticket);
+
+/* Non-blocking: *done = 1 when the request has finished, with its status and
+ * latency in seconds (submit to completion). */
+zmc_status zmc_server_poll(zmc_server* server, uint64_t ticket, int32_t* done,
+                           zmc_status* result, double* latency_s);
+
+/* Blocks until the request has finished. */
+zmc_status zmc_server_wait(zmc_server* server, uint64_t ticket, zmc_status* result,
+                           double* latency_s);
+
+zmc_status zmc_server_get_stats(zmc_server* server, zmc_server_stats* stats);
+
+/* Finishes every submitted request, stops the thread, frees the server. */
+zmc_status zmc_server_destroy(zmc_server* server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,16 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libzmc.so")
-SOURCES = ["zmc_api.hip", "zmc_kernels.hip"]
+FAMILIES = ("SinSum", "Gauss", "CosExp", "Const", "Linear")
+REALS = ("float", "double")
+# (source, extra defines, object name): the family kernels build one
+# translation unit per (family, precision) so that they compile in parallel
+SOURCES = ([("zmc_api.hip", (), "zmc_api"), ("zmc_batch.hip", (), "zmc_batch"),
+            ("zmc_tune.hip", (), "zmc_tune"), ("zmc_kernels.hip", (), "zmc_kernels"),
+            ("zmc_server.hip", (), "zmc_server")]
+           + [("zmc_family.hip", (f"-DZMC_FAMILY={f}", f"-DZMC_REAL={r}"), f"zmc_{f}_{r}")
+              for f in FAMILIES for r in REALS]
+           + [("zmc_any.hip", (f"-DZMC_REAL={r}",), f"zmc_any_{r}") for r in REALS])
 ARCH = "gfx950"
 
 
@@ -31,15 +40,16 @@ def flags():
             "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
 
 
-def build(out=LIB, jobs=8, verbose=False):
+def build(out=LIB, jobs=None, verbose=False):
     """Compile every source and link `out`; returns its path."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     cc = hipcc()
 
-    def compile_one(src):
-        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [cc, *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+    def compile_one(entry):
+        src, defines, name = entry
+        obj = os.path.join(objdir, name + ".o")
+        cmd = [cc, *flags(), *defines, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -47,6 +57,8 @@ def build(out=LIB, jobs=8, verbose=False):
             print(r.stderr)
         return obj
 
+    if jobs is None:
+        jobs = max(1, min(16, os.cpu_count() or 1))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = out + ".tmp"

@@ -13,8 +13,10 @@
 #include "zmc_internal.hpp"
 
 namespace {
-
 thread_local char g_err[512] = "";
+}  // namespace
+
+namespace zmc {
 
 zmc_status fail(zmc_status st, const char* fmt, ...) {
   va_list ap;
@@ -28,6 +30,13 @@ zmc_status ok() {
   g_err[0] = '\0';
   return ZMC_OK;
 }
+
+}  // namespace zmc
+
+namespace {
+
+using zmc::fail;
+using zmc::ok;
 
 #define ZMC_HIP(call)                                                              \
   do {                                                                             \
@@ -209,6 +218,19 @@ void fill_params(const zmc_scan_desc* d, uint64_t G, const zmc::Plan& pl, const 
   p->sigma = d_sigma;
 }
 
+}  // namespace
+
+namespace zmc {
+zmc_status validate_desc(const zmc_scan_desc* d, uint64_t* G) { return validate(d, G); }
+zmc_status cu_count(int* cu) { return device_cu_count(cu); }
+void fill_scan_params(const zmc_scan_desc* d, uint64_t G, const Plan& pl, const double* d_axis,
+                      double* d_f, double* d_sigma, ScanParams* p) {
+  fill_params(d, G, pl, d_axis, d_f, d_sigma, p);
+}
+}  // namespace zmc
+
+namespace {
+
 void to_info(const zmc::Plan& pl, uint64_t G, zmc_plan_info* out) {
   memset(out, 0, sizeof(*out));
   out->mode = pl.mode;
@@ -295,8 +317,8 @@ zmc_status zmc_scan(const zmc_scan_desc* desc, double* f, double* sigma) {
   if (e == hipSuccess && total > 0)
     e = hipMemcpy(d_axis, desc->axis_vals, total * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    hipFree(d_axis);
-    hipFree(d_out);
+    (void)hipFree(d_axis);
+    (void)hipFree(d_out);
     return fail(e == hipErrorOutOfMemory ? ZMC_E_NOMEM : ZMC_E_DEVICE, "staging failed: %s",
                 hipGetErrorString(e));
   }
@@ -306,8 +328,8 @@ zmc_status zmc_scan(const zmc_scan_desc* desc, double* f, double* sigma) {
     if (e == hipSuccess) e = hipMemcpy(sigma, d_out + G, G * sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) st = fail(ZMC_E_DEVICE, "copy back failed: %s", hipGetErrorString(e));
   }
-  hipFree(d_axis);
-  hipFree(d_out);
+  (void)hipFree(d_axis);
+  (void)hipFree(d_out);
   return st == ZMC_OK ? ok() : st;
 }
 

@@ -38,6 +38,17 @@ struct ScanParams {
   double* part_m2;
 };
 
+// One unit of batched work: a point-major tile (256 consecutive grid points
+// of one scan over one sample piece) or a sample-major tile (one grid point,
+// one sample piece, the whole block).
+struct Tile {
+  uint32_t scan;        // index into the batch's scan table
+  uint32_t split_mode;  // bits 0..30: sample piece; bit 31: 1 = sample-major
+  uint64_t first;       // point-major: first grid point; sample-major: the point
+};
+
+constexpr uint32_t kTileSampleMajor = 0x80000000u;
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  A round takes the high
 // and low halves of the products of words 0 and 2 with the two multipliers
@@ -386,8 +397,8 @@ __device__ __forceinline__ void eval_group(const Fam& fam, uint64_t j, const Gen
 
 // ---------------------------------------------------------------------------
 // Per-lane accumulation: shifted sums of d = v - c and d^2 in T, each with a
-// Kahan compensation term, four samples at a time.  c is the integrand at the
-// box centre, which keeps the final M2 = S2 - S1^2 / n well conditioned.
+// Kahan compensation term, four samples at a time.  c is one of the lane's own
+// samples, which keeps the final M2 = S2 - S1^2 / n well conditioned.
 // ---------------------------------------------------------------------------
 template <typename T> struct LaneAcc {
   T c;

@@ -24,6 +24,41 @@ struct Plan {
 
 hipError_t launch_scan(const ScanParams& p, const Plan& plan, int precision, hipStream_t stream,
                        hipEvent_t ev_begin, hipEvent_t ev_end);
+struct Tile;
+
+// Host helpers shared by the single-scan and the batched entry points.
+zmc_status fail(zmc_status st, const char* fmt, ...);
+zmc_status ok();
+zmc_status validate_desc(const zmc_scan_desc* d, uint64_t* G);
+zmc_status cu_count(int* cu);
+void fill_scan_params(const zmc_scan_desc* d, uint64_t G, const Plan& pl, const double* d_axis,
+                      double* d_f, double* d_sigma, ScanParams* p);
+
+// Tuned tile shapes of one kernel variant (family, precision, N).
+struct TuneEntry {
+  int64_t pm_groups;      // groups of four samples per lane in a point-major tile
+  int64_t sm_groups;      // groups per sample-major tile (all lanes of the block)
+  int64_t pm_min_points;  // grids smaller than this use sample-major tiles
+};
+TuneEntry tune_lookup(int family, int precision, int N);
+
+constexpr int kTileBlock = 256;
+constexpr uint64_t kMaxPartialBytesPerScan = (uint64_t)2 << 30;
+zmc_status plan_tiles(const zmc_scan_desc* d, uint64_t G, int64_t pm_groups_override,
+                      int64_t sm_groups_override, int64_t pm_min_override, Plan* pl,
+                      uint64_t* tiles);
+const char* tune_source();
+hipError_t batch_occupancy(int precision, int family, int N, int* blocks_per_cu);
+hipError_t launch_batch_variant(int precision, int family, int N, const ScanParams* scans,
+                                const Tile* tiles, uint32_t begin, uint32_t end,
+                                uint32_t* counter, unsigned blocks, hipStream_t stream);
+hipError_t batch_any_occupancy(int precision, int* blocks_per_cu);
+hipError_t launch_batch_any(int precision, const ScanParams* scans, const Tile* tiles,
+                            uint32_t begin, uint32_t end, uint32_t* counter, unsigned blocks,
+                            hipStream_t stream);
+hipError_t launch_reset_counters(uint32_t* counters, int n, hipStream_t stream);
+hipError_t launch_merge_batch(const ScanParams* scans, const uint32_t* merge_scans, int n_merge,
+                              uint64_t max_points, hipStream_t stream);
 hipError_t launch_debug_words(uint64_t seed, uint64_t g, uint64_t w0, int64_t count,
                               uint32_t* out, hipStream_t stream);
 hipError_t launch_debug_values(const ScanParams& p, int precision, uint64_t g, uint64_t s0,

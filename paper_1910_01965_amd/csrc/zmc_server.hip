@@ -1,0 +1,530 @@
+// zmc_server.hip -- serving with continuous batching (include/zmc.h).
+//
+// A scheduler thread owns two HIP streams and alternates short slices
+// between them so that the next slice's blocks start while the previous
+// slice's last tiles finish.  Every slice takes tiles round-robin from all
+// admitted requests (each request cut into the same tiles a batch would use)
+// and runs them in one persistent kernel per precision; requests whose last
+// tile is in the slice get their split merge in the same slice and complete
+// when its event does.  Admission is FIFO, limited by the HBM budget for the
+// requests' own device state (staged lists and split partials) and by the
+// number of slots in the device table of scan descriptors.
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "zmc.h"
+#include "zmc_device.hpp"
+#include "zmc_internal.hpp"
+
+using zmc::fail;
+using zmc::ok;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  uint64_t ticket = 0;
+  zmc_scan_desc desc{};
+  std::vector<int64_t> axis_len;
+  std::vector<double> axis_vals, lo, hi;
+  const double* d_axis_user = nullptr;
+  double* d_f = nullptr;
+  double* d_sigma = nullptr;
+  uint64_t G = 0;
+  zmc::Plan plan{};
+  uint64_t total_tiles = 0, next_tile = 0;
+  uint64_t staged_doubles = 0;
+  uint64_t footprint = 0;
+  void* dmem = nullptr;
+  int alloc_stream = 0;
+  int slot = -1;
+  Clock::time_point t_submit;
+  double latency = 0.0;
+  zmc_status status = ZMC_OK;
+  bool done = false;
+};
+
+using ReqPtr = std::shared_ptr<Request>;
+
+struct Slice {
+  hipEvent_t done_ev = nullptr;
+  std::vector<ReqPtr> finishing;
+};
+
+constexpr int kStreams = 2;
+
+}  // namespace
+
+struct zmc_server {
+  zmc_server_opts opts{};
+  int device = 0;
+  hipStream_t streams[kStreams] = {nullptr, nullptr};
+  unsigned blocks32 = 1, blocks64 = 1;
+  int ring = 3;
+  // device memory: slot table | tile ring | counter ring | merge ring
+  void* dmem = nullptr;
+  zmc::ScanParams* d_slots = nullptr;
+  zmc::Tile* d_tiles = nullptr;
+  uint32_t* d_counters = nullptr;
+  uint32_t* d_merge = nullptr;
+  // pinned host mirrors
+  zmc::ScanParams* h_slots = nullptr;
+  zmc::Tile* h_tiles = nullptr;
+  uint32_t* h_merge = nullptr;
+  std::vector<hipEvent_t> done_events, admit_events;
+  // shared with submitters
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<ReqPtr> incoming;
+  std::unordered_map<uint64_t, ReqPtr> tickets;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  zmc_server_stats stats{};
+  // scheduler-thread state
+  std::deque<ReqPtr> pending, active;
+  std::deque<Slice> inflight;
+  std::vector<int> free_slots;
+  uint64_t bytes_in_use = 0;
+  uint64_t slice_count = 0;
+  std::thread thread;
+};
+
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+zmc::Tile tile_of(const Request& r, uint64_t t) {
+  const bool pm = r.plan.mode == ZMC_MODE_POINT_MAJOR;
+  const uint64_t per = pm ? r.plan.point_blocks : r.G;
+  const uint64_t split = t / per, i = t % per;
+  zmc::Tile tl;
+  tl.scan = (uint32_t)r.slot;
+  tl.split_mode = (uint32_t)split | (pm ? 0u : zmc::kTileSampleMajor);
+  tl.first = pm ? i * zmc::kTileBlock : i;
+  return tl;
+}
+
+void finish(zmc_server* s, const ReqPtr& r, zmc_status st) {
+  r->latency = std::chrono::duration<double>(Clock::now() - r->t_submit).count();
+  std::lock_guard<std::mutex> lk(s->mu);
+  r->status = st;
+  r->done = true;
+  if (st == ZMC_OK) {
+    s->stats.completed++;
+    s->stats.samples_completed += r->G * r->desc.samples;
+  } else {
+    s->stats.failed++;
+  }
+  s->cv_done.notify_all();
+}
+
+// Admission: device state, staged lists, the slot's scan descriptor.
+hipError_t admit(zmc_server* s, const ReqPtr& r, int si) {
+  hipStream_t st = s->streams[si];
+  hipError_t e = hipSuccess;
+  if (r->footprint > 0) e = hipMallocAsync(&r->dmem, r->footprint, st);
+  if (e != hipSuccess) return e;
+  r->alloc_stream = si;
+  char* base = (char*)r->dmem;
+  const double* axis = r->d_axis_user;
+  if (axis == nullptr && r->staged_doubles > 0) {
+    e = hipMemcpyAsync(base, r->axis_vals.data(), 8 * r->staged_doubles, hipMemcpyHostToDevice, st);
+    axis = (const double*)base;
+  }
+  r->slot = s->free_slots.back();
+  s->free_slots.pop_back();
+  zmc::ScanParams& p = s->h_slots[r->slot];
+  zmc::fill_scan_params(&r->desc, r->G, r->plan, axis, r->d_f, r->d_sigma, &p);
+  if (r->plan.splits > 1) {
+    double* pm = (double*)(base + align_up(8 * r->staged_doubles));
+    p.part_mean = pm;
+    p.part_m2 = pm + (uint64_t)r->plan.splits * r->G;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_slots + r->slot, &p, sizeof(p), hipMemcpyHostToDevice, st);
+  return e;
+}
+
+// One slice on stream `si`: tiles round-robin over the admitted requests
+// (an equal share each, then what is left in admission order), FP32 tiles
+// then FP64 tiles, one persistent kernel for each; then the split merges of
+// the requests whose last tile is in the slice.
+hipError_t launch_slice(zmc_server* s, int si, Slice* out) {
+  const uint32_t cap = (uint32_t)s->opts.slice_tiles;
+  const int ring_slot = (int)(s->slice_count % (uint64_t)s->ring);
+  zmc::Tile* ht = s->h_tiles + (size_t)ring_slot * cap;
+  std::vector<std::pair<ReqPtr, uint64_t>> take;
+  size_t with_work = 0;
+  for (const ReqPtr& r : s->active)
+    if (r->next_tile < r->total_tiles) ++with_work;
+  if (with_work == 0) return hipSuccess;
+  const uint64_t share = std::max<uint64_t>(1, cap / with_work);
+  uint64_t used = 0;
+  for (const ReqPtr& r : s->active) {
+    const uint64_t left = r->total_tiles - r->next_tile;
+    const uint64_t k = std::min<uint64_t>({left, share, cap - used});
+    if (k > 0) take.emplace_back(r, k), used += k;
+  }
+  for (auto& tk : take) {
+    const uint64_t left = tk.first->total_tiles - tk.first->next_tile - tk.second;
+    const uint64_t more = std::min<uint64_t>(left, cap - used);
+    tk.second += more;
+    used += more;
+  }
+  uint32_t n32 = 0, n = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int prec = pass == 0 ? ZMC_FP32_MERGE64 : ZMC_FP64;
+    for (auto& tk : take) {
+      Request& r = *tk.first;
+      if (r.desc.precision != prec) continue;
+      for (uint64_t t = 0; t < tk.second; ++t) ht[n++] = tile_of(r, r.next_tile + t);
+    }
+    if (pass == 0) n32 = n;
+  }
+  std::vector<uint32_t> merges;
+  uint64_t max_g = 0;
+  out->finishing.clear();
+  for (auto& tk : take) {
+    Request& r = *tk.first;
+    r.next_tile += tk.second;
+    if (r.next_tile == r.total_tiles) {
+      out->finishing.push_back(tk.first);
+      if (r.plan.splits > 1) merges.push_back((uint32_t)r.slot), max_g = std::max(max_g, r.G);
+    }
+  }
+  hipStream_t st = s->streams[si];
+  zmc::Tile* dt = s->d_tiles + (size_t)ring_slot * cap;
+  uint32_t* dc = s->d_counters + 2 * ring_slot;
+  // the other stream's admissions (slot table, staged lists) come first
+  hipError_t e = hipStreamWaitEvent(st, s->admit_events[1 - si], 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(dt, ht, sizeof(zmc::Tile) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = zmc::launch_reset_counters(dc, 2, st);
+  if (e == hipSuccess && n32 > 0)
+    e = zmc::launch_batch_any(ZMC_FP32_MERGE64, s->d_slots, dt, 0, n32, dc, s->blocks32, st);
+  if (e == hipSuccess && n > n32)
+    e = zmc::launch_batch_any(ZMC_FP64, s->d_slots, dt, n32, n, dc + 1, s->blocks64, st);
+  if (e == hipSuccess && !merges.empty()) {
+    // a finishing request's earlier tiles may sit in the other stream's slice
+    if (s->slice_count > 0) e = hipStreamWaitEvent(st, s->done_events[(ring_slot + s->ring - 1) % s->ring], 0);
+    uint32_t* hm = s->h_merge + (size_t)ring_slot * (size_t)s->opts.max_slots;
+    std::copy(merges.begin(), merges.end(), hm);
+    uint32_t* dm = s->d_merge + (size_t)ring_slot * (size_t)s->opts.max_slots;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dm, hm, sizeof(uint32_t) * merges.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = zmc::launch_merge_batch(s->d_slots, dm, (int)merges.size(), max_g, st);
+  }
+  if (e == hipSuccess) e = hipEventRecord(s->done_events[ring_slot], st);
+  out->done_ev = s->done_events[ring_slot];
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->stats.slices++;
+  s->stats.tiles += n;
+  return e;
+}
+
+void retire(zmc_server* s, Slice& sl) {
+  for (const ReqPtr& r : sl.finishing) {
+    if (r->dmem) (void)hipFreeAsync(r->dmem, s->streams[r->alloc_stream]);
+    r->dmem = nullptr;
+    s->bytes_in_use -= r->footprint;
+    s->free_slots.push_back(r->slot);
+    finish(s, r, ZMC_OK);
+  }
+  s->active.erase(std::remove_if(s->active.begin(), s->active.end(),
+                                 [](const ReqPtr& r) { return r->done; }),
+                  s->active.end());
+}
+
+void fail_all(zmc_server* s, zmc_status st) {
+  for (Slice& sl : s->inflight)
+    for (const ReqPtr& r : sl.finishing)
+      if (!r->done) finish(s, r, st);
+  s->inflight.clear();
+  for (const ReqPtr& r : s->active)
+    if (!r->done) finish(s, r, st);
+  s->active.clear();
+  for (const ReqPtr& r : s->pending) finish(s, r, st);
+  s->pending.clear();
+}
+
+void run(zmc_server* s) {
+  (void)hipSetDevice(s->device);
+  bool broken = false;
+  for (;;) {
+    bool stopping;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      while (!s->incoming.empty()) {
+        s->pending.push_back(s->incoming.front());
+        s->incoming.pop_front();
+      }
+      stopping = s->stop;
+    }
+    if (broken) {
+      fail_all(s, ZMC_E_DEVICE);
+      if (stopping) break;
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_work.wait_for(lk, std::chrono::milliseconds(50));
+      continue;
+    }
+    bool progressed = false;
+    while (!s->inflight.empty()) {
+      const hipError_t q = hipEventQuery(s->inflight.front().done_ev);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) {
+        broken = true;
+        break;
+      }
+      retire(s, s->inflight.front());
+      s->inflight.pop_front();
+      progressed = true;
+    }
+    if (broken) continue;
+    const int si = (int)(s->slice_count % kStreams);
+    bool admitted = false;
+    while (!s->pending.empty() && !s->free_slots.empty()) {
+      ReqPtr r = s->pending.front();
+      if (r->footprint > s->opts.hbm_budget_bytes) {
+        s->pending.pop_front();
+        finish(s, r, ZMC_E_NOMEM);
+        continue;
+      }
+      if (s->bytes_in_use + r->footprint > s->opts.hbm_budget_bytes) break;
+      s->pending.pop_front();
+      if (admit(s, r, si) != hipSuccess) {
+        finish(s, r, ZMC_E_DEVICE);
+        broken = true;
+        break;
+      }
+      s->bytes_in_use += r->footprint;
+      s->active.push_back(r);
+      admitted = progressed = true;
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stats.admitted++;
+      s->stats.bytes_in_use = s->bytes_in_use;
+      s->stats.bytes_peak = std::max(s->stats.bytes_peak, s->bytes_in_use);
+    }
+    if (broken) continue;
+    if (admitted && hipEventRecord(s->admit_events[si], s->streams[si]) != hipSuccess) {
+      broken = true;
+      continue;
+    }
+    if ((int)s->inflight.size() < s->opts.max_inflight) {
+      Slice sl;
+      if (launch_slice(s, si, &sl) != hipSuccess) {
+        broken = true;
+        continue;
+      }
+      if (sl.done_ev != nullptr) {
+        s->inflight.push_back(std::move(sl));
+        s->slice_count++;
+        progressed = true;
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stats.pending = s->pending.size() + s->incoming.size();
+      s->stats.active = s->active.size();
+      s->stats.bytes_in_use = s->bytes_in_use;
+    }
+    if (stopping && s->pending.empty() && s->active.empty() && s->inflight.empty()) break;
+    if (!progressed) {
+      if (!s->inflight.empty()) {
+        if (hipEventSynchronize(s->inflight.front().done_ev) != hipSuccess) broken = true;
+      } else {
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_work.wait_for(lk, std::chrono::milliseconds(20),
+                            [&] { return !s->incoming.empty() || s->stop; });
+      }
+    }
+  }
+  for (int i = 0; i < kStreams; ++i) (void)hipStreamSynchronize(s->streams[i]);
+}
+
+void release(zmc_server* s) {
+  for (hipEvent_t ev : s->done_events)
+    if (ev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : s->admit_events)
+    if (ev) (void)hipEventDestroy(ev);
+  for (int i = 0; i < kStreams; ++i)
+    if (s->streams[i]) (void)hipStreamDestroy(s->streams[i]);
+  if (s->dmem) (void)hipFree(s->dmem);
+  if (s->h_slots) (void)hipHostFree(s->h_slots);
+  if (s->h_tiles) (void)hipHostFree(s->h_tiles);
+  if (s->h_merge) (void)hipHostFree(s->h_merge);
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+zmc_status zmc_server_create(const zmc_server_opts* opts, zmc_server** out) {
+  if (out == nullptr) return fail(ZMC_E_INVALID, "out is NULL");
+  *out = nullptr;
+  zmc_server* s = new (std::nothrow) zmc_server();
+  if (s == nullptr) return fail(ZMC_E_NOMEM, "host allocation failed");
+  if (opts) s->opts = *opts;
+  zmc_server_opts& o = s->opts;
+  if (o.hbm_budget_bytes == 0) o.hbm_budget_bytes = (uint64_t)64 << 30;
+  if (o.max_slots <= 0) o.max_slots = 256;
+  if (o.max_inflight <= 0) o.max_inflight = 2;
+  if (o.max_slots > 65536 || o.max_inflight > 16) {
+    delete s;
+    return fail(ZMC_E_INVALID, "max_slots <= 65536 and max_inflight <= 16 required");
+  }
+  s->ring = o.max_inflight + 1;
+  hipError_t e = hipGetDevice(&s->device);
+  int cu = o.cu_count;
+  if (e == hipSuccess && cu <= 0) {
+    zmc_status st = zmc::cu_count(&cu);
+    if (st != ZMC_OK) {
+      delete s;
+      return st;
+    }
+  }
+  int per32 = 1, per64 = 1;
+  if (e == hipSuccess) e = zmc::batch_any_occupancy(ZMC_FP32_MERGE64, &per32);
+  if (e == hipSuccess) e = zmc::batch_any_occupancy(ZMC_FP64, &per64);
+  s->blocks32 = (unsigned)std::max(1, cu * std::max(1, per32));
+  s->blocks64 = (unsigned)std::max(1, cu * std::max(1, per64));
+  if (o.slice_tiles <= 0) o.slice_tiles = (int32_t)(4 * s->blocks32);
+  const size_t cap = (size_t)o.slice_tiles, ring = (size_t)s->ring, slots = (size_t)o.max_slots;
+  const size_t off_tiles = align_up(sizeof(zmc::ScanParams) * slots);
+  const size_t off_counters = off_tiles + align_up(sizeof(zmc::Tile) * cap * ring);
+  const size_t off_merge = off_counters + align_up(sizeof(uint32_t) * 2 * ring);
+  const size_t total = off_merge + align_up(sizeof(uint32_t) * slots * ring);
+  if (e == hipSuccess) e = hipMalloc(&s->dmem, total);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_slots, sizeof(zmc::ScanParams) * slots, 0);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_tiles, sizeof(zmc::Tile) * cap * ring, 0);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_merge, sizeof(uint32_t) * slots * ring, 0);
+  for (int i = 0; e == hipSuccess && i < kStreams; ++i)
+    e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
+  s->done_events.assign(ring, nullptr);
+  s->admit_events.assign(kStreams, nullptr);
+  for (size_t i = 0; e == hipSuccess && i < ring; ++i)
+    e = hipEventCreateWithFlags(&s->done_events[i], hipEventDisableTiming | hipEventBlockingSync);
+  for (int i = 0; e == hipSuccess && i < kStreams; ++i) {
+    e = hipEventCreateWithFlags(&s->admit_events[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(s->admit_events[i], s->streams[i]);
+  }
+  if (e != hipSuccess) {
+    release(s);
+    return fail(ZMC_E_DEVICE, "server setup failed: %s", hipGetErrorString(e));
+  }
+  char* base = (char*)s->dmem;
+  s->d_slots = (zmc::ScanParams*)base;
+  s->d_tiles = (zmc::Tile*)(base + off_tiles);
+  s->d_counters = (uint32_t*)(base + off_counters);
+  s->d_merge = (uint32_t*)(base + off_merge);
+  for (int i = o.max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
+  try {
+    s->thread = std::thread(run, s);
+  } catch (...) {
+    release(s);
+    return fail(ZMC_E_NOMEM, "could not start the scheduler thread");
+  }
+  *out = s;
+  return ok();
+}
+
+zmc_status zmc_server_submit(zmc_server* s, const zmc_scan_desc* desc, const double* d_axis_vals,
+                             double* d_f, double* d_sigma, uint64_t* ticket) {
+  if (s == nullptr || ticket == nullptr) return fail(ZMC_E_INVALID, "NULL server or ticket");
+  uint64_t G = 0;
+  zmc_status st = zmc::validate_desc(desc, &G);
+  if (st != ZMC_OK) return st;
+  if (d_f == nullptr || d_sigma == nullptr) return fail(ZMC_E_INVALID, "d_f or d_sigma is NULL");
+  if (desc->M > 0 && d_axis_vals == nullptr && desc->axis_vals == nullptr)
+    return fail(ZMC_E_INVALID, "no parameter lists (host or device)");
+  auto r = std::make_shared<Request>();
+  r->desc = *desc;
+  r->axis_len.assign(desc->axis_len, desc->axis_len + desc->M);
+  uint64_t total = 0;
+  for (int l = 0; l < desc->M; ++l) total += (uint64_t)desc->axis_len[l];
+  if (d_axis_vals == nullptr) {
+    r->axis_vals.assign(desc->axis_vals, desc->axis_vals + total);
+    r->staged_doubles = total;
+  }
+  r->lo.assign(desc->lo, desc->lo + desc->N);
+  r->hi.assign(desc->hi, desc->hi + desc->N);
+  r->desc.axis_len = r->axis_len.data();
+  r->desc.axis_vals = r->axis_vals.empty() ? nullptr : r->axis_vals.data();
+  r->desc.lo = r->lo.data();
+  r->desc.hi = r->hi.data();
+  r->desc.params = nullptr;
+  r->d_axis_user = d_axis_vals;
+  r->d_f = d_f;
+  r->d_sigma = d_sigma;
+  r->G = G;
+  st = zmc::plan_tiles(&r->desc, G, 0, 0, 0, &r->plan, &r->total_tiles);
+  if (st != ZMC_OK) return st;
+  r->footprint = align_up(8 * r->staged_doubles) + r->plan.workspace_bytes;
+  r->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return fail(ZMC_E_BUSY, "server is shutting down");
+    r->ticket = s->next_ticket++;
+    s->tickets[r->ticket] = r;
+    s->incoming.push_back(r);
+    s->stats.submitted++;
+  }
+  s->cv_work.notify_one();
+  *ticket = r->ticket;
+  return ok();
+}
+
+zmc_status zmc_server_poll(zmc_server* s, uint64_t ticket, int32_t* done, zmc_status* result,
+                           double* latency_s) {
+  if (s == nullptr || done == nullptr) return fail(ZMC_E_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return fail(ZMC_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  *done = it->second->done ? 1 : 0;
+  if (result) *result = it->second->done ? it->second->status : ZMC_OK;
+  if (latency_s) *latency_s = it->second->done ? it->second->latency : 0.0;
+  return ok();
+}
+
+zmc_status zmc_server_wait(zmc_server* s, uint64_t ticket, zmc_status* result, double* latency_s) {
+  if (s == nullptr) return fail(ZMC_E_INVALID, "NULL server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return fail(ZMC_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  ReqPtr r = it->second;
+  s->cv_done.wait(lk, [&] { return r->done; });
+  if (result) *result = r->status;
+  if (latency_s) *latency_s = r->latency;
+  return ok();
+}
+
+zmc_status zmc_server_get_stats(zmc_server* s, zmc_server_stats* stats) {
+  if (s == nullptr || stats == nullptr) return fail(ZMC_E_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *stats = s->stats;
+  return ok();
+}
+
+zmc_status zmc_server_destroy(zmc_server* s) {
+  if (s == nullptr) return ok();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->thread.joinable()) s->thread.join();
+  release(s);
+  return ok();
+}
+
+}  // extern "C"

@@ -21,7 +21,11 @@ STATUS = {0: "ZMC_OK", 1: "ZMC_E_INVALID", 2: "ZMC_E_NOMEM", 3: "ZMC_E_DEVICE",
           4: "ZMC_E_UNSUPPORTED", 5: "ZMC_E_BUSY"}
 
 EXPORTS = ("zmc_last_error", "zmc_version", "zmc_validate", "zmc_plan", "zmc_scan",
-           "zmc_scan_device", "zmc_scan_device_ex", "zmc_debug_words", "zmc_debug_values")
+           "zmc_scan_device", "zmc_scan_device_ex", "zmc_debug_words", "zmc_debug_values",
+           "zmc_batch_default_opts", "zmc_batch_plan", "zmc_batch_create", "zmc_batch_launch",
+           "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch", "zmc_tune_source",
+           "zmc_server_create", "zmc_server_submit", "zmc_server_poll", "zmc_server_wait",
+           "zmc_server_get_stats", "zmc_server_destroy")
 
 
 class ZmcError(RuntimeError):
@@ -61,6 +65,32 @@ class PlanInfo(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_uint64)]
 
 
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("use_graph", ctypes.c_int32), ("parallel_variants", ctypes.c_int32),
+                ("pm_groups", ctypes.c_int64), ("sm_groups", ctypes.c_int64),
+                ("pm_min_points", ctypes.c_int64), ("cu_count", ctypes.c_int32),
+                ("one_kernel", ctypes.c_int32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("scans", ctypes.c_int32), ("variants", ctypes.c_int32), ("tiles", ctypes.c_int64),
+                ("samples", ctypes.c_uint64), ("points", ctypes.c_uint64),
+                ("workspace_bytes", ctypes.c_uint64), ("merge_scans", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
+                ("slice_tiles", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("cu_count", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in (
+        "submitted", "admitted", "completed", "failed", "pending", "active", "samples_completed",
+        "slices", "tiles", "bytes_in_use", "bytes_peak")]
+
+
 _lib = None
 
 
@@ -86,8 +116,33 @@ def load():
                                         ctypes.c_int64, vp, vp]
         lib.zmc_debug_values.argtypes = [descp, vp, ctypes.c_uint64, ctypes.c_uint64,
                                          ctypes.c_int64, vp, vp]
+        ptrs = ctypes.POINTER(ctypes.c_void_p)
+        lib.zmc_batch_default_opts.argtypes = [ctypes.POINTER(BatchOpts)]
+        lib.zmc_batch_default_opts.restype = None
+        lib.zmc_batch_plan.argtypes = [descp, ctypes.c_int32, ctypes.POINTER(BatchOpts),
+                                       ctypes.POINTER(BatchInfo)]
+        lib.zmc_batch_create.argtypes = [descp, ctypes.c_int32, ptrs, ptrs, ptrs,
+                                         ctypes.POINTER(BatchOpts), ctypes.POINTER(vp)]
+        lib.zmc_batch_launch.argtypes = [vp, vp]
+        lib.zmc_batch_get_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+        lib.zmc_batch_destroy.argtypes = [vp]
+        lib.zmc_scan_batch.argtypes = [descp, ctypes.c_int32, ptrs, ptrs, ptrs, vp]
+        lib.zmc_tune_source.restype = ctypes.c_char_p
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        lib.zmc_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+        lib.zmc_server_submit.argtypes = [vp, descp, vp, vp, vp, u64p]
+        lib.zmc_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+        lib.zmc_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_double)]
+        lib.zmc_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        lib.zmc_server_destroy.argtypes = [vp]
         for name in ("zmc_validate", "zmc_plan", "zmc_scan", "zmc_scan_device",
-                     "zmc_scan_device_ex", "zmc_debug_words", "zmc_debug_values"):
+                     "zmc_scan_device_ex", "zmc_debug_words", "zmc_debug_values",
+                     "zmc_batch_plan", "zmc_batch_create", "zmc_batch_launch",
+                     "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch",
+                     "zmc_server_create", "zmc_server_submit", "zmc_server_poll",
+                     "zmc_server_wait", "zmc_server_get_stats", "zmc_server_destroy"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -219,3 +274,169 @@ def debug_values(spec, g, s0, count, stream=None):
                                    int(s0), int(count), ctypes.c_void_p(out.data_ptr()),
                                    _stream_ptr(stream)))
     return out
+
+
+# ---------------------------------------------------------------- batches ---
+def _batch_opts(use_graph=True, parallel_variants=True, pm_groups=0, sm_groups=0,
+                pm_min_points=0, cu_count=0, one_kernel=False):
+    o = BatchOpts()
+    load().zmc_batch_default_opts(ctypes.byref(o))
+    o.use_graph = int(bool(use_graph))
+    o.parallel_variants = int(bool(parallel_variants))
+    o.pm_groups, o.sm_groups, o.pm_min_points = int(pm_groups), int(sm_groups), int(pm_min_points)
+    o.cu_count = int(cu_count)
+    o.one_kernel = int(bool(one_kernel))
+    return o
+
+
+def _info_dict(info):
+    return {k: getattr(info, k) for k, _ in BatchInfo._fields_}
+
+
+class _DescArray:
+    """A contiguous C array of descriptors for a list of ScanSpecs."""
+
+    def __init__(self, specs):
+        self.descs = [Desc(sp) for sp in specs]
+        self.arr = (ScanDesc * len(specs))(*[d.c for d in self.descs])
+
+
+def batch_plan(specs, **opts):
+    """Host-only plan of a batch: tiles, variants, workspace (dict)."""
+    da = _DescArray(specs)
+    o = _batch_opts(**opts)
+    info = BatchInfo()
+    _check(load().zmc_batch_plan(da.arr, len(specs), ctypes.byref(o), ctypes.byref(info)))
+    return _info_dict(info)
+
+
+class Batch:
+    """Many scans captured once in a hipGraph; `launch` replays it.
+
+    outputs: list of (f, sigma) float64 device tensors (allocated when None);
+    axes: list of device tensors holding each scan's lists (staged by the
+    library from the specs when None)."""
+
+    def __init__(self, specs, outputs=None, axes=None, **opts):
+        import torch
+        self.specs = list(specs)
+        n = len(self.specs)
+        if outputs is None:
+            outputs = []
+            for sp in self.specs:
+                G = validate(sp)
+                outputs.append((torch.empty(G, dtype=torch.float64, device="cuda"),
+                                torch.empty(G, dtype=torch.float64, device="cuda")))
+        self.outputs = outputs
+        self.axes = axes
+        self._da = _DescArray(self.specs)
+        P = ctypes.c_void_p * n
+        self._f = P(*[f.data_ptr() for f, _ in outputs])
+        self._s = P(*[s.data_ptr() for _, s in outputs])
+        self._a = P(*[a.data_ptr() for a in axes]) if axes is not None else None
+        o = _batch_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(load().zmc_batch_create(self._da.arr, n, self._a, self._f, self._s, ctypes.byref(o),
+                                       ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(load().zmc_batch_launch(self._h, _stream_ptr(stream)))
+
+    def info(self):
+        info = BatchInfo()
+        _check(load().zmc_batch_get_info(self._h, ctypes.byref(info)))
+        return _info_dict(info)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().zmc_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def scan_batch(specs, **opts):
+    """Run a batch once and return its [(f, sigma)] device tensors."""
+    import torch
+    b = Batch(specs, **opts)
+    b.launch()
+    torch.cuda.synchronize()
+    out = b.outputs
+    b.close()
+    return out
+
+
+def tune_source():
+    return load().zmc_tune_source().decode()
+
+
+# ---------------------------------------------------------------- serving ---
+class Server:
+    """Continuous-batching request loop (zmc_server_*).  `submit` returns a
+    ticket immediately; outputs are float64 device tensors that must stay
+    alive until the request completes (the Server keeps a reference)."""
+
+    def __init__(self, hbm_budget_bytes=0, max_slots=0, slice_tiles=0, max_inflight=0, cu_count=0):
+        o = ServerOpts(int(hbm_budget_bytes), int(max_slots), int(slice_tiles), int(max_inflight),
+                       int(cu_count))
+        h = ctypes.c_void_p()
+        _check(load().zmc_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, spec, f=None, sigma=None, axis=None):
+        import torch
+        G = validate(spec)
+        if f is None:
+            f = torch.empty(G, dtype=torch.float64, device="cuda")
+        if sigma is None:
+            sigma = torch.empty(G, dtype=torch.float64, device="cuda")
+        d = Desc(spec)
+        t = ctypes.c_uint64()
+        _check(load().zmc_server_submit(self._h, d.ref,
+                                        ctypes.c_void_p(axis.data_ptr()) if axis is not None else None,
+                                        ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(sigma.data_ptr()),
+                                        ctypes.byref(t)))
+        self._keep[t.value] = (f, sigma, axis)
+        return t.value
+
+    def outputs(self, ticket):
+        f, s, _ = self._keep[ticket]
+        return f, s
+
+    def poll(self, ticket):
+        """(done, status, latency_s)."""
+        done = ctypes.c_int32()
+        st = ctypes.c_int()
+        lat = ctypes.c_double()
+        _check(load().zmc_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(st),
+                                      ctypes.byref(lat)))
+        return bool(done.value), st.value, lat.value
+
+    def wait(self, ticket):
+        """(status, latency_s) once the request has finished."""
+        st = ctypes.c_int()
+        lat = ctypes.c_double()
+        _check(load().zmc_server_wait(self._h, ticket, ctypes.byref(st), ctypes.byref(lat)))
+        return st.value, lat.value
+
+    def stats(self):
+        st = ServerStats()
+        _check(load().zmc_server_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().zmc_server_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -118,3 +118,29 @@ def test_bad_launch_options(lib):
     for kw in ({"block": 100}, {"block": 2048}, {"mode": "point_major", "block": 512}):
         with pytest.raises(zmc.ZmcError):
             zmc.plan(GOOD, cu_count=256, **kw)
+
+
+def test_batch_plan_on_cpu(lib):
+    specs = wl.batched_512()
+    info = zmc.batch_plan(specs, cu_count=256)
+    assert info["scans"] == 512 and 1 <= info["variants"] <= 21
+    assert info["points"] == sum(s.G for s in specs)
+    assert info["samples"] == sum(s.G * s.samples for s in specs)
+    # tile count: point-major tiles of 256 points x ceil(groups / pm_groups) pieces
+    one = [wl.gauss_2p(points_per_axis=100, samples=10_000)]
+    p = zmc.batch_plan(one, cu_count=256, pm_groups=100)
+    assert p["tiles"] == ((10_000 // 256) + 1) * 25 and p["merge_scans"] == 1
+    p = zmc.batch_plan(one, cu_count=256, pm_groups=10_000)
+    assert p["tiles"] == (10_000 // 256) + 1 and p["merge_scans"] == 0
+    p = zmc.batch_plan(one, cu_count=256, pm_min_points=10**9, sm_groups=625)
+    assert p["tiles"] == 10_000 * 4
+
+
+def test_batch_plan_names_the_bad_scan(lib):
+    specs = wl.batched_512()[:5]
+    specs[3] = specs[3].with_(samples=1)
+    with pytest.raises(zmc.ZmcError) as ei:
+        zmc.batch_plan(specs, cu_count=256)
+    assert ei.value.status == 1 and "scan 3" in str(ei.value)
+    with pytest.raises(zmc.ZmcError):
+        zmc.batch_plan([], cu_count=256)

@@ -1,0 +1,136 @@
+"""The serving loop (continuous batching) on the GPU: every request's result
+is bitwise the same alone and in the mix, matches the oracle, admission
+respects the HBM budget, and requests that can never fit fail cleanly."""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as zo
+from paper_1910_01965_amd import workloads as wl
+
+import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_01965_amd import zmc
+    zmc.load()
+    return torch
+
+
+def _zmc():
+    from paper_1910_01965_amd import zmc
+    return zmc
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _requests(count, seed=7, max_samples=1 << 14):
+    """Request shapes of the 512-scan batch generator, sample counts capped so
+    the test stays short; a few FP64 requests and a ragged one mixed in."""
+    specs = wl.batched_512(count=count, seed=seed)
+    out = []
+    for i, sp in enumerate(specs):
+        sp = sp.with_(samples=min(sp.samples, max_samples), seed=1000 + i)
+        if i % 5 == 4:
+            sp = sp.with_(precision="fp64")
+        if i % 7 == 3:
+            sp = sp.with_(samples=sp.samples + 3)
+        out.append(sp)
+    return out
+
+
+def _alone(spec):
+    f, s = _zmc().scan_batch([spec])[0]
+    return f.cpu().numpy(), s.cpu().numpy()
+
+
+def test_mix_equals_alone_and_oracle():
+    import torch
+    zmc = _zmc()
+    specs = _requests(24)
+    srv = zmc.Server(max_slots=8, slice_tiles=512)
+    tickets = []
+    for i, sp in enumerate(specs):
+        tickets.append(srv.submit(sp))
+        if i % 6 == 5:
+            time.sleep(0.01)  # arrivals while earlier requests are on the GPU
+    lat = []
+    for t in tickets:
+        st, l = srv.wait(t)
+        assert st == 0
+        lat.append(l)
+    stats = srv.stats()
+    _say(f"serving: {stats}; latency p50 {np.median(lat) * 1e3:.1f} ms max {max(lat) * 1e3:.1f} ms")
+    assert stats["completed"] == len(specs) and stats["failed"] == 0
+    assert stats["slices"] > 1
+    torch.cuda.synchronize()
+    for i, (sp, t) in enumerate(zip(specs, tickets)):
+        f, s = srv.outputs(t)
+        f, s = f.cpu().numpy(), s.cpu().numpy()
+        fa, sa = _alone(sp)
+        assert np.array_equal(f, fa) and np.array_equal(s, sa), (i, sp.name)
+        if i % 4 == 0:
+            idx = np.sort(np.random.default_rng(i).choice(sp.G, min(sp.G, 6), replace=False))
+            f_ref, s_ref = zo.scan(sp, idx.astype(np.uint64))
+            parity.check(f[idx], s[idx], f_ref, s_ref, sp.samples, sp.precision, sp.name)
+    srv.close()
+
+
+def test_budget_admission_and_oversized_request():
+    zmc = _zmc()
+    specs = _requests(10, seed=8)
+    plans = [zmc.batch_plan([sp]) for sp in specs]
+    need = [p["workspace_bytes"] for p in plans]
+    budget = int(max(need) * 1.5) + (1 << 20)
+    srv = zmc.Server(hbm_budget_bytes=budget, max_slots=4, slice_tiles=256)
+    tickets = [srv.submit(sp) for sp in specs]
+    for t in tickets:
+        st, _ = srv.wait(t)
+        assert st == 0
+    stats = srv.stats()
+    _say(f"budget {budget}: {stats}")
+    assert stats["bytes_peak"] <= budget and stats["completed"] == len(specs)
+    # a request whose own state exceeds the budget fails, the server carries on
+    big = wl.gauss_2p(points_per_axis=1000, samples=1 << 16)
+    t_big = srv.submit(big)
+    t_ok = srv.submit(specs[0])
+    st_big, _ = srv.wait(t_big)
+    st_ok, _ = srv.wait(t_ok)
+    assert st_big == 2 and st_ok == 0
+    srv.close()
+
+
+def test_concurrent_submitters():
+    zmc = _zmc()
+    specs = _requests(16, seed=9, max_samples=1 << 12)
+    srv = zmc.Server(max_slots=16)
+    tickets = [None] * len(specs)
+
+    def worker(k):
+        for i in range(k, len(specs), 4):
+            tickets[i] = srv.submit(specs[i])
+
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for t in tickets:
+        assert srv.wait(t)[0] == 0
+    for sp, t in zip(specs[::5], tickets[::5]):
+        f, s = srv.outputs(t)
+        fa, sa = _alone(sp)
+        assert np.array_equal(f.cpu().numpy(), fa) and np.array_equal(s.cpu().numpy(), sa)
+    srv.close()
