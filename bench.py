@@ -87,6 +87,90 @@ def time_path(spec, steps, warmup):
                 plan=zmc.plan(spec))
 
 
+def batched_run(reps=1):
+    """The 512-scan batch in one captured graph vs the same scans launched
+    back to back through the plain entry point."""
+    import torch
+    from paper_1910_01965_amd import workloads as wl
+    from paper_1910_01965_amd import zmc
+    specs = wl.batched_512()
+    total = sum(sp.G * sp.samples for sp in specs)
+    outs = [(torch.empty(sp.G, dtype=torch.float64, device="cuda"),
+             torch.empty(sp.G, dtype=torch.float64, device="cuda")) for sp in specs]
+    b = zmc.Batch(specs, outputs=outs)
+    info = b.info()
+    b.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.launch()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    b.close()
+    axes = [zmc.axis_tensor(sp) for sp in specs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (f, s), sp, a in zip(outs, specs, axes):
+        zmc.scan_device(sp, a, f, s)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    return {"value": total / t_batch, "unit": "samples/s", "seconds": t_batch,
+            "plain_back_to_back": total / t_plain, "ratio_vs_plain": t_plain / t_batch,
+            "scans": len(specs), "samples": total, "tiles": info["tiles"],
+            "variants": info["variants"], "graph": bool(info["graph"]),
+            "grid_pts_per_s": sum(sp.G for sp in specs) / t_batch}
+
+
+def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=32, compare_plain=False):
+    """Poisson arrivals of scans shaped like the 512-scan batch (family,
+    N, grid size, samples drawn by default_rng(seed); request i has Philox
+    seed i) into the continuous-batching server; latency = completion -
+    submission.  Optionally the same request trace back to back through
+    the plain entry point."""
+    import torch
+    from paper_1910_01965_amd import workloads as wl
+    from paper_1910_01965_amd import zmc
+    rng = np.random.default_rng(seed)
+    t_arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * duration * 3) + 16))
+    t_arr = t_arr[t_arr < duration]
+    n_req = len(t_arr)
+    specs = [sp.with_(seed=i) for i, sp in enumerate(wl.batched_512(count=n_req, seed=seed))]
+    total = sum(sp.G * sp.samples for sp in specs)
+    srv = zmc.Server(hbm_budget_bytes=budget, max_slots=max_slots)
+    tickets = []
+    t0 = time.perf_counter()
+    for ta, sp in zip(t_arr, specs):
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        tickets.append(srv.submit(sp))
+    lat = np.array([srv.wait(t)[1] for t in tickets])
+    t_all = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    out = {"rate_per_s": rate, "arrival_seconds": duration, "requests": n_req, "samples": total,
+           "value": total / t_all, "unit": "samples/s", "wall_seconds": t_all,
+           "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                         "mean": float(lat.mean()), "max": float(lat.max())},
+           "slices": stats["slices"], "bytes_peak": stats["bytes_peak"],
+           "budget_bytes": budget, "max_slots": max_slots}
+    if compare_plain:
+        outs = [(torch.empty(sp.G, dtype=torch.float64, device="cuda"),
+                 torch.empty(sp.G, dtype=torch.float64, device="cuda")) for sp in specs]
+        axes = [zmc.axis_tensor(sp) for sp in specs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for (f, s), sp, a in zip(outs, specs, axes):
+            zmc.scan_device(sp, a, f, s)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        out["plain_back_to_back"] = total / t_plain
+        # the server's device-busy throughput is bounded by arrivals only if it
+        # ever idles; under overload it is total / (wall - first arrival gap)
+        out["ratio_vs_plain"] = (total / t_all) / (total / t_plain)
+    return out
+
+
 def cpu_baseline(spec, points, seed=0):
     from oracle import oracle as zo
     idx = np.sort(np.random.default_rng(seed).choice(spec.G, points, replace=False)).astype(np.uint64)
@@ -119,6 +203,10 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--cpu-points", type=int, default=48000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=4.0,
+                    help="arrival window of the serving runs (the full workload is 60 s)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -179,6 +267,25 @@ def main():
         "roofline": roofline,
         "finite": r32["finite"] and r64["finite"],
     }
+    if not args.no_batched:
+        log("batched: 512 scans")
+        out["batched"] = batched_run()
+        log(f"batched: {out['batched']['value']:.4g} samples/s ({out['batched']['ratio_vs_plain']:.3f}x plain)")
+    if not args.no_serving:
+        log(f"serving: 200 req/s for {args.serve_seconds} s")
+        over = serving_run(200.0, args.serve_seconds, compare_plain=True)
+        log(f"serving overload: {over['value']:.4g} samples/s, p50 {over['latency_s']['p50']:.3f} s, "
+            f"p99 {over['latency_s']['p99']:.3f} s")
+        cap = out["batched"]["value"] if "batched" in out else over["plain_back_to_back"]
+        mean_req = over["samples"] / max(1, over["requests"])
+        steady_rate = 0.7 * cap / mean_req
+        log(f"serving steady: {steady_rate:.1f} req/s for {2 * args.serve_seconds} s")
+        steady = serving_run(steady_rate, 2 * args.serve_seconds, seed=8)
+        out["serving"] = {"overload_200_per_s": over, "steady_0p7_capacity": steady,
+                          "what": "Poisson arrivals of 512-batch-shaped scans, 64 GiB budget, "
+                                  "32 slots; latency = completion - submission"}
+        out["latency_ms"]["serving_p50"] = steady["latency_s"]["p50"] * 1e3
+        out["latency_ms"]["serving_p99"] = steady["latency_s"]["p99"] * 1e3
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_points} points")
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_points)

@@ -23,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tune_table.txt")
 PM_CANDIDATES = (128, 256, 512, 1024, 2048, 4096, 8192)
 SM_GROUPS = 16384
-PM_MIN_CANDIDATES = (32, 64, 128, 256, 512)
+PM_MIN_CANDIDATES = (128, 512, 2048, 8192, 32768)
 
 
 def _time_batch(zmc, specs, reps, **opts):
@@ -60,20 +60,21 @@ def tune_pm_groups(zmc, specs, reps, log):
 
 
 def tune_pm_min(zmc, family, precision, N, pm_groups, reps, log):
+    """Smallest grid at which point-major tiles beat sample-major tiles for
+    one scan running alone (2^14 samples): below it a grid's point-major
+    tiles are too few to fill the GPU."""
     from . import workloads as wl
-    choice = PM_MIN_CANDIDATES[-1]
+    choice = 2 * PM_MIN_CANDIDATES[-1]
+    M = wl.family_shape(family, N, 2, 4, 0, precision).M
     for G in PM_MIN_CANDIDATES:
-        sp = wl.family_shape(family, N, 2, 1 << 16, 7, precision)
-        M = sp.M
         L = max(2, int(round(G ** (1.0 / M))))
-        sp = wl.family_shape(family, N, L, 1 << 16, 7, precision)
-        specs = [sp.with_(seed=i) for i in range(8)]
-        t_pm = _time_batch(zmc, specs, reps, pm_groups=pm_groups, pm_min_points=1)
-        t_sm = _time_batch(zmc, specs, reps, pm_groups=pm_groups, pm_min_points=1 << 40,
+        sp = wl.family_shape(family, N, L, 1 << 14, 7, precision)
+        t_pm = _time_batch(zmc, [sp], reps, pm_groups=pm_groups, pm_min_points=1)
+        t_sm = _time_batch(zmc, [sp], reps, pm_groups=pm_groups, pm_min_points=1 << 40,
                            sm_groups=SM_GROUPS)
         log(f"    G={sp.G}: point-major {t_pm * 1e3:.2f} ms, sample-major {t_sm * 1e3:.2f} ms")
         if t_pm <= t_sm:
-            choice = G
+            choice = sp.G
             break
     return choice
 
