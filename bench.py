@@ -204,6 +204,7 @@ def main():
     ap.add_argument("--cpu-points", type=int, default=48000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="arrival window of the serving runs (the full workload is 60 s)")
@@ -267,6 +268,21 @@ def main():
         "roofline": roofline,
         "finite": r32["finite"] and r64["finite"],
     }
+    if not args.no_configs:
+        out["configs"] = {}
+        for name, sp, steps in (("plain_fp64_1000pts_n65536", wl.plain_fp64(), 20),
+                                ("cosexp_4p_1e8pts_n4096_fp32", wl.cosexp_4p(precision="fp32"), 2),
+                                ("cosexp_4p_1e8pts_n4096_fp64", wl.cosexp_4p(precision="fp64"), 1)):
+            log(f"config {name}: {steps} steps")
+            r = time_path(sp, steps, 1)
+            ms = r["wall_s"] * 1e3 / steps
+            km = float(np.mean(r["kernel_ms"]))
+            w = valu_ops_per_sample(sp.family, sp.N)
+            out["configs"][name] = {
+                "samples_per_s": sp.G * sp.samples / (ms / 1e3), "grid_pts_per_s": sp.G / (ms / 1e3),
+                "ms_per_step": ms, "kernel_ms": km, "plan": r["plan"],
+                "valu_frac": w * sp.G * sp.samples / (km / 1e3) / VALU_PEAK if sp.precision == "fp32" else None}
+            log(f"  {out['configs'][name]['samples_per_s']:.4g} samples/s, {ms:.3f} ms/step")
     if not args.no_batched:
         log("batched: 512 scans")
         out["batched"] = batched_run()
