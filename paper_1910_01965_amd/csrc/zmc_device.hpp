@@ -217,6 +217,40 @@ template <> __device__ __forceinline__ float fmaT(float a, float b, float c) {
 
 constexpr double kLog2e = 1.4426950408889634074;
 
+// FP32 sine and cosine of a phase x through the hardware units, which take
+// their argument in revolutions.  The phase is reduced to [-1/2, 1/2]
+// revolutions with a two-term product by 1/(2 pi) (Cody-Waite style): with
+// r = x c_hi rounded, e = (x c_hi - r) + x c_lo recovered by two fmas, the
+// reduced phase is t = (r - rint(r)) + e, where r - rint(r) is exact; t is
+// off by little more than its own final rounding (2^-25 revolutions at most)
+// for |x| < 2^20.  Larger phases take the library routine.  Six VALU
+// instructions and one transcendental in place of the library's argument
+// reduction and polynomial.
+constexpr float kInv2PiHi = 0.15915494f;                 // float(1/(2 pi))
+constexpr float kInv2PiLo = (float)(0.15915494309189533577 - (double)0.15915494f);
+constexpr float kFastTrigMax = 0x1p20f;
+
+__device__ __forceinline__ float reduce_rev(float x) {
+  // no contraction here: fusing r - rint(r) into fma(x, c_hi, -rint(r))
+  // would count the rounding error of r twice
+#pragma clang fp contract(off)
+  const float r = x * kInv2PiHi;
+  const float e = __builtin_fmaf(x, kInv2PiLo, __builtin_fmaf(x, kInv2PiHi, -r));
+  return (r - __builtin_rintf(r)) + e;
+}
+
+__device__ __forceinline__ float sin_rev(float x) {
+  float s = __builtin_amdgcn_sinf(reduce_rev(x));
+  if (__builtin_expect(__builtin_fabsf(x) >= kFastTrigMax, 0)) s = sinf(x);
+  return s;
+}
+
+__device__ __forceinline__ float cos_rev(float x) {
+  float c = __builtin_amdgcn_cosf(reduce_rev(x));
+  if (__builtin_expect(__builtin_fabsf(x) >= kFastTrigMax, 0)) c = cosf(x);
+  return c;
+}
+
 // Parameter x_l of grid point g (C order: stride_l = prod_{j>l} L_j).
 __device__ __forceinline__ double param_x(const ScanParams& p, uint64_t g, int l) {
   const uint64_t i = (g / p.axis_stride[l]) % (uint64_t)p.axis_len[l];
@@ -257,7 +291,7 @@ template <typename T, int N> struct SinSum {
       float ph = sx;
 #pragma unroll
       for (int k = 0; k < N; ++k) ph = fmaT(A[k], t[k], ph);
-      return sinf(ph);
+      return sin_rev(ph);
     }
   }
 };
@@ -329,7 +363,7 @@ template <typename T, int N> struct CosExp {
       for (int k = 2; k < N; ++k) ph = fmaT(A[k], t[k], ph);
       ph = fmaT(x1, y1, fmaT(x2, y2, ph));
       const float e = __builtin_amdgcn_exp2f(nx3sq * y1 * y2);
-      return fmaT(cosf(ph), e, x4);
+      return fmaT(cos_rev(ph), e, x4);
     }
   }
 };
