@@ -62,7 +62,11 @@ def tune_pm_groups(zmc, specs, reps, log):
 def tune_pm_min(zmc, family, precision, N, pm_groups, reps, log):
     """Smallest grid at which point-major tiles beat sample-major tiles for
     one scan running alone (2^14 samples): below it a grid's point-major
-    tiles are too few to fill the GPU."""
+    tiles are too few to fill the GPU.  Judged alone, the threshold serves
+    the latency of small requests (a small grid alone finishes several times
+    sooner in sample-major tiles); in a large batch, where point-major tiles
+    of every size keep the GPU full, scans below it carry only a small share
+    of the samples."""
     from . import workloads as wl
     choice = 2 * PM_MIN_CANDIDATES[-1]
     M = wl.family_shape(family, N, 2, 4, 0, precision).M
@@ -109,9 +113,11 @@ def main(argv=None):
                 pm = tune_pm_groups(zmc, specs, args.reps, log)
                 pmin = tune_pm_min(zmc, family, precision, N, pm, args.reps, log)
                 rows.append((family, precision, N, pm, SM_GROUPS, pmin))
+    props = torch.cuda.get_device_properties(0)
     with open(args.out + ".tmp", "w") as fh:
         fh.write("# zmc tile-shape table, written by paper_1910_01965_amd/autotune.py on "
-                 f"{torch.cuda.get_device_name(0)} ({torch.cuda.get_device_properties(0).multi_processor_count} CUs)\n")
+                 f"{torch.cuda.get_device_name(0)} ({getattr(props, 'gcnArchName', '?')}, "
+                 f"{props.multi_processor_count} CUs)\n")
         fh.write("# family precision N pm_groups sm_groups pm_min_points\n")
         for r in rows:
             fh.write(" ".join(str(x) for x in r) + "\n")
