@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace zmc {
 
 constexpr int kMaxParams = 16;
@@ -297,19 +299,62 @@ template <typename T, int N> struct SinSum {
 };
 
 // exp(-(sum_{k<=M} x_k y_k^2 + sum_{k>M} y_k^2)).
+// With every coefficient c_k of a point finite and >= 0 (c_k = x_k for k <= M,
+// 1 beyond; times log2(e) in FP32), sqrt(c_k) is folded into that point's
+// affine map, z_k = sqrt(c_k) y_k, and the point stores c_k = 1, so that the
+// one formula fma(c_k y, y, q) gives sum_k z_k^2.  The tile loops run waves
+// whose points are all folded on GaussUnit, which drops the product with
+// c_k = 1 and so changes no bit: a point's value depends on that point alone.
+template <typename T, int N> struct GaussUnit {
+  T A[N], B[N];
+  __device__ __forceinline__ T value(const T* t) const {
+    T q = (T)0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const T z = fmaT(A[k], t[k], B[k]);
+      q = fmaT(z, z, q);
+    }
+    if constexpr (sizeof(T) == 8) {
+      return exp(-q);
+    } else {
+      return __builtin_amdgcn_exp2f(-q);
+    }
+  }
+};
+
 template <typename T, int N> struct Gauss {
   static constexpr int kMinDims = 1;
+  using UnitForm = GaussUnit<T, N>;
   T A[N], B[N], c[N];   // FP32: c carries log2(e) for exp2
+  bool unit;            // wave-uniform: c_k = 1 on every active lane of the wave
   __device__ void setup(const ScanParams& p, uint64_t g) {
+    double x[N];
+    bool fold = true;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      x[k] = (k < p.M) ? param_x(p, g, k) : 1.0;
+      fold = fold && x[k] >= 0.0 && x[k] <= 0x1.fffffffffffffp+1023;
+    }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       double a, b;
       Unif<T>::affine(p.lo[k], p.hi[k], &a, &b);
-      A[k] = (T)a;
-      B[k] = (T)b;
-      const double x = (k < p.M) ? param_x(p, g, k) : 1.0;
-      c[k] = sizeof(T) == 8 ? (T)x : (T)(x * kLog2e);
+      const double ck = sizeof(T) == 8 ? x[k] : x[k] * kLog2e;
+      const double s = fold ? sqrt(ck) : 1.0;
+      A[k] = (T)(a * s);
+      B[k] = (T)(b * s);
+      c[k] = fold ? (T)1 : (T)ck;
     }
+    unit = __builtin_amdgcn_ballot_w64(!fold) == 0;
+  }
+  __device__ __forceinline__ UnitForm unit_form() const {
+    UnitForm u;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      u.A[k] = A[k];
+      u.B[k] = B[k];
+    }
+    return u;
   }
   __device__ __forceinline__ T value(const T* t) const {
     T q = (T)0;
@@ -427,6 +472,24 @@ __device__ __forceinline__ void eval_group(const Fam& fam, uint64_t j, const Gen
   }
 #pragma unroll
   for (int s = 0; s < 4; ++s) v[s] = fam.value(t + s * N);
+}
+
+// Runs body(f) with f = the family's reduced form (Fam::UnitForm) when the
+// family has one and its wave-uniform `unit` flag is set, else with fam
+// itself; the two give the same bits, the reduced form in fewer instructions.
+template <class Fam, class = void> struct HasUnitForm : std::false_type {};
+template <class Fam>
+struct HasUnitForm<Fam, std::void_t<typename Fam::UnitForm>> : std::true_type {};
+
+template <class Fam, class Body>
+__device__ __forceinline__ void with_form(const Fam& fam, Body&& body) {
+  if constexpr (HasUnitForm<Fam>::value) {
+    if (fam.unit) {
+      body(fam.unit_form());
+      return;
+    }
+  }
+  body(fam);
 }
 
 // ---------------------------------------------------------------------------

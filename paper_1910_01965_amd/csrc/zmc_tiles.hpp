@@ -69,13 +69,16 @@ __device__ __forceinline__ void pm_tile(const ScanParams& p, uint64_t first, uin
   fam.setup(p, g);
   LaneAcc<T> acc;
   acc.init((T)0);
-  if (p.fast_counter) {
-    const GenPointMajor gen{philox_lane((uint32_t)g, p.seed)};
-    lane_groups<Fam, T, N>(fam, gen, j0, jfull, ragged, tail, acc);
-  } else {
-    const GenAny gen{g, p.seed};
-    lane_groups<Fam, T, N>(fam, gen, j0, jfull, ragged, tail, acc);
-  }
+  with_form(fam, [&](const auto& f) {
+    using F = std::decay_t<decltype(f)>;
+    if (p.fast_counter) {
+      const GenPointMajor gen{philox_lane((uint32_t)g, p.seed)};
+      lane_groups<F, T, N>(f, gen, j0, jfull, ragged, tail, acc);
+    } else {
+      const GenAny gen{g, p.seed};
+      lane_groups<F, T, N>(f, gen, j0, jfull, ragged, tail, acc);
+    }
+  });
   const Moments m = to_moments(acc, (double)split_samples(p.n, p.n_groups, p.gps, sp));
   if (p.splits == 1) {
     finalize(p, g, m);
@@ -102,18 +105,21 @@ __device__ __forceinline__ void sm_tile(const ScanParams& p, uint64_t g, uint64_
   acc.init((T)0);
   double count = 0.0;
   const GenAny gen{g, p.seed};
-  for (uint64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
-    T v[4];
-    eval_group<Fam, T, N>(fam, j, gen, v);
-    if (count == 0.0) acc.init(v[0]);  // shift by the lane's first sample
-    if (j == last && tail != 4) {
-      acc.add_partial(v, tail);
-      count += (double)tail;
-    } else {
-      acc.add4(v);
-      count += 4.0;
+  with_form(fam, [&](const auto& f) {
+    using F = std::decay_t<decltype(f)>;
+    for (uint64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+      T v[4];
+      eval_group<F, T, N>(f, j, gen, v);
+      if (count == 0.0) acc.init(v[0]);  // shift by the lane's first sample
+      if (j == last && tail != 4) {
+        acc.add_partial(v, tail);
+        count += (double)tail;
+      } else {
+        acc.add4(v);
+        count += 4.0;
+      }
     }
-  }
+  });
   Moments m = wave_merge(to_moments(acc, count));
   const unsigned w = threadIdx.x >> 6;
   if ((threadIdx.x & 63u) == 0) {

@@ -128,10 +128,13 @@ def test_batch_plan_on_cpu(lib):
     assert info["samples"] == sum(s.G * s.samples for s in specs)
     # tile count: point-major tiles of 256 points x ceil(groups / pm_groups) pieces
     one = [wl.gauss_2p(points_per_axis=100, samples=10_000)]
-    p = zmc.batch_plan(one, cu_count=256, pm_groups=100)
+    p = zmc.batch_plan(one, cu_count=256, pm_groups=100, pm_min_points=1)
     assert p["tiles"] == ((10_000 // 256) + 1) * 25 and p["merge_scans"] == 1
-    p = zmc.batch_plan(one, cu_count=256, pm_groups=10_000)
+    p = zmc.batch_plan(one, cu_count=256, pm_groups=10_000, pm_min_points=1)
     assert p["tiles"] == (10_000 // 256) + 1 and p["merge_scans"] == 0
+    # grids below the point-major threshold: one tile per point and piece
+    p = zmc.batch_plan(one, cu_count=256, pm_min_points=10_001, sm_groups=1000)
+    assert p["tiles"] == 10_000 * 3 and p["merge_scans"] == 1
     p = zmc.batch_plan(one, cu_count=256, pm_min_points=10**9, sm_groups=625)
     assert p["tiles"] == 10_000 * 4
 

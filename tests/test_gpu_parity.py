@@ -198,6 +198,46 @@ def test_repeatable_bitwise():
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["point_major", "sample_major"])
+def test_gauss_signed_coefficients(precision, mode):
+    """GAUSS with negative, zero and positive coefficients on one grid: waves
+    of all-nonnegative points take the reduced form, mixed waves the general
+    one; both against the oracle."""
+    # 60 points per row: waves straddle rows, so rows with x1 < 0 next to rows
+    # with x1 >= 0 give mixed waves; x2 starts at exactly 0
+    spec = wl.ScanSpec("gauss", [np.linspace(-0.6, 2.0, 41), np.linspace(0.0, 1.5, 60)],
+                       np.array([-0.5, 0.0, -1.0]), np.array([1.0, 1.5, 0.5]), 2048, 12, precision)
+    _say(f"gauss signed coefficients {precision} {mode}")
+    f, s = _run(spec, mode=mode)
+    f_ref, s_ref = zo.scan(spec)
+    _, _, msg = parity.check(f, s, f_ref, s_ref, spec.samples, precision, spec.name)
+    _say(msg)
+    for g in (0, 30 * 60, spec.G - 1):  # x1 < 0; x1 > 0 with x2 = 0; both > 0
+        got = _zmc().debug_values(spec, g, 5, 40).cpu().numpy()
+        ref = zo.values(spec, g, 5, 40)
+        tol = 1e-14 if precision == "fp64" else 4e-6 * spec.N
+        assert np.all(np.abs(got - ref) <= tol * (1.0 + np.abs(ref))), g
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_gauss_point_independent_of_its_wave(precision):
+    """A point's result does not depend on the other points of its wave:
+    making one coefficient of a 256-point grid negative moves that wave off
+    the reduced form, and every other point keeps its bits."""
+    xs = np.linspace(0.05, 4.0, 256)
+    a = wl.ScanSpec("gauss", [xs], np.zeros(3), np.ones(3), 4096, 13, precision)
+    ys = xs.copy()
+    ys[70] = -0.5
+    b = a.with_(axes=[ys])
+    fa, sa = _run(a, mode="point_major", splits=2)
+    fb, sb = _run(b, mode="point_major", splits=2)
+    keep = np.arange(256) != 70
+    assert np.array_equal(fa[keep], fb[keep]) and np.array_equal(sa[keep], sb[keep])
+    f_ref, s_ref = zo.scan(b)
+    parity.check(fb, sb, f_ref, s_ref, b.samples, precision, "gauss one negative coefficient")
+
+
 EDGE = [
     wl.ScanSpec("sin_sum", [], np.zeros(3), np.ones(3), 1001, 5),            # M = 0, G = 1
     wl.ScanSpec("sin_sum", [np.linspace(0, 1, 7)], np.zeros(1), np.ones(1), 2, 5),
