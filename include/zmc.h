@@ -270,9 +270,13 @@ typedef struct zmc_server_opts {
   uint64_t hbm_budget_bytes;   /* device-state budget of admitted requests
                                   (0 = 64 GiB)                               */
   int32_t max_slots;           /* admitted requests at once (0 = 256)        */
-  int32_t slice_tiles;         /* tiles per slice (0 = 4 per resident block) */
+  int32_t slice_tiles;         /* at most this many tiles per slice
+                                  (0 = 64 per resident block)                */
   int32_t max_inflight;        /* slices enqueued ahead of the device (0 = 2) */
   int32_t cu_count;            /* compute units (0 = device)                 */
+  uint64_t slice_samples;      /* samples per slice, shared equally among
+                                  the admitted requests, the rest oldest
+                                  first (0 = 4e9, a few ms of device time)    */
 } zmc_server_opts;
 
 typedef struct zmc_server_stats {

@@ -44,6 +44,7 @@ struct Request {
   uint64_t G = 0;
   zmc::Plan plan{};
   uint64_t total_tiles = 0, next_tile = 0;
+  uint64_t tile_samples = 1;  // samples per tile, averaged over the request's tiles
   uint64_t staged_doubles = 0;
   uint64_t footprint = 0;
   void* dmem = nullptr;
@@ -156,12 +157,15 @@ hipError_t admit(zmc_server* s, const ReqPtr& r, int si) {
   return e;
 }
 
-// One slice on stream `si`: tiles round-robin over the admitted requests
-// (an equal share each, then what is left in admission order), FP32 tiles
-// then FP64 tiles, one persistent kernel for each; then the split merges of
-// the requests whose last tile is in the slice.
+// One slice on stream `si`: work round-robin over the admitted requests (an
+// equal share of the slice's samples each, then what is left in admission
+// order), FP32 tiles then FP64 tiles, one persistent kernel for each; then
+// the split merges of the requests whose last tile is in the slice.  Slices
+// are sized in samples, not tiles, because a request's tiles range from one
+// point's sample piece to 256 points' pieces.
 hipError_t launch_slice(zmc_server* s, int si, Slice* out) {
-  const uint32_t cap = (uint32_t)s->opts.slice_tiles;
+  const uint64_t cap = (uint64_t)s->opts.slice_tiles;
+  const uint64_t budget = s->opts.slice_samples;
   const int ring_slot = (int)(s->slice_count % (uint64_t)s->ring);
   zmc::Tile* ht = s->h_tiles + (size_t)ring_slot * cap;
   std::vector<std::pair<ReqPtr, uint64_t>> take;
@@ -169,18 +173,23 @@ hipError_t launch_slice(zmc_server* s, int si, Slice* out) {
   for (const ReqPtr& r : s->active)
     if (r->next_tile < r->total_tiles) ++with_work;
   if (with_work == 0) return hipSuccess;
-  const uint64_t share = std::max<uint64_t>(1, cap / with_work);
-  uint64_t used = 0;
+  const uint64_t share = std::max<uint64_t>(1, budget / with_work);
+  uint64_t used = 0, used_samples = 0;
   for (const ReqPtr& r : s->active) {
     const uint64_t left = r->total_tiles - r->next_tile;
-    const uint64_t k = std::min<uint64_t>({left, share, cap - used});
-    if (k > 0) take.emplace_back(r, k), used += k;
+    const uint64_t want = (share + r->tile_samples - 1) / r->tile_samples;
+    const uint64_t k = std::min<uint64_t>({left, want, cap - used});
+    if (k > 0) take.emplace_back(r, k), used += k, used_samples += k * r->tile_samples;
   }
   for (auto& tk : take) {
-    const uint64_t left = tk.first->total_tiles - tk.first->next_tile - tk.second;
-    const uint64_t more = std::min<uint64_t>(left, cap - used);
+    if (used_samples >= budget || used >= cap) break;
+    const Request& r = *tk.first;
+    const uint64_t left = r.total_tiles - r.next_tile - tk.second;
+    const uint64_t want = (budget - used_samples + r.tile_samples - 1) / r.tile_samples;
+    const uint64_t more = std::min<uint64_t>({left, want, cap - used});
     tk.second += more;
     used += more;
+    used_samples += more * r.tile_samples;
   }
   uint32_t n32 = 0, n = 0;
   for (int pass = 0; pass < 2; ++pass) {
@@ -398,7 +407,8 @@ zmc_status zmc_server_create(const zmc_server_opts* opts, zmc_server** out) {
   if (e == hipSuccess) e = zmc::batch_any_occupancy(ZMC_FP64, &per64);
   s->blocks32 = (unsigned)std::max(1, cu * std::max(1, per32));
   s->blocks64 = (unsigned)std::max(1, cu * std::max(1, per64));
-  if (o.slice_tiles <= 0) o.slice_tiles = (int32_t)(4 * s->blocks32);
+  if (o.slice_tiles <= 0) o.slice_tiles = (int32_t)std::min<uint64_t>(64ull * s->blocks32, 1u << 20);
+  if (o.slice_samples == 0) o.slice_samples = 4000000000ull;
   const size_t cap = (size_t)o.slice_tiles, ring = (size_t)s->ring, slots = (size_t)o.max_slots;
   const size_t off_tiles = align_up(sizeof(zmc::ScanParams) * slots);
   const size_t off_counters = off_tiles + align_up(sizeof(zmc::Tile) * cap * ring);
@@ -469,6 +479,8 @@ zmc_status zmc_server_submit(zmc_server* s, const zmc_scan_desc* desc, const dou
   r->G = G;
   st = zmc::plan_tiles(&r->desc, G, 0, 0, 0, &r->plan, &r->total_tiles);
   if (st != ZMC_OK) return st;
+  r->tile_samples = (uint64_t)std::max(
+      1.0, (double)G * (double)desc->samples / (double)std::max<uint64_t>(1, r->total_tiles));
   r->footprint = align_up(8 * r->staged_doubles) + r->plan.workspace_bytes;
   r->t_submit = Clock::now();
   {

@@ -82,7 +82,7 @@ class BatchInfo(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
                 ("slice_tiles", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
-                ("cu_count", ctypes.c_int32)]
+                ("cu_count", ctypes.c_int32), ("slice_samples", ctypes.c_uint64)]
 
 
 class ServerStats(ctypes.Structure):
@@ -381,9 +381,10 @@ class Server:
     ticket immediately; outputs are float64 device tensors that must stay
     alive until the request completes (the Server keeps a reference)."""
 
-    def __init__(self, hbm_budget_bytes=0, max_slots=0, slice_tiles=0, max_inflight=0, cu_count=0):
+    def __init__(self, hbm_budget_bytes=0, max_slots=0, slice_tiles=0, max_inflight=0, cu_count=0,
+                 slice_samples=0):
         o = ServerOpts(int(hbm_budget_bytes), int(max_slots), int(slice_tiles), int(max_inflight),
-                       int(cu_count))
+                       int(cu_count), int(slice_samples))
         h = ctypes.c_void_p()
         _check(load().zmc_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h
