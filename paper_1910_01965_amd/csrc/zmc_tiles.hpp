@@ -294,8 +294,19 @@ struct FamilyOps {
     return hipGetLastError();
   }
 
-  // Instances below a family's smallest N (COSEXP needs two dimensions) are
-  // never built; validation rejects those descriptors before dispatch.
+  // Dispatch on N.  Defined out of line (not inline), so that the explicit
+  // instantiation declarations below keep every other translation unit from
+  // instantiating the kernels again.
+  static hipError_t main(int N, const ScanParams& p, const Plan& plan, hipStream_t stream);
+  static hipError_t values(int N, const ScanParams& p, uint64_t g, uint64_t s0, int64_t count,
+                           double* out, hipStream_t stream);
+  static hipError_t occupancy(int N, int* blocks_per_cu);
+  static hipError_t batch(int N, const ScanParams* scans, const Tile* tiles, uint32_t begin,
+                          uint32_t end, uint32_t* counter, unsigned blocks, hipStream_t stream);
+};
+
+// Instances below a family's smallest N (COSEXP needs two dimensions) are
+// never built; validation rejects those descriptors before dispatch.
 #define ZMC_BY_DIMS(CALL)                                                           \
   switch (N) {                                                                      \
     case 1: if constexpr (1 >= F<T, 1>::kMinDims) return CALL(1); else break;       \
@@ -310,44 +321,58 @@ struct FamilyOps {
   }                                                                                 \
   return hipErrorInvalidValue;
 
-  static hipError_t main(int N, const ScanParams& p, const Plan& plan, hipStream_t stream) {
+template <template <typename, int> class F, typename T>
+hipError_t FamilyOps<F, T>::main(int N, const ScanParams& p, const Plan& plan, hipStream_t stream) {
 #define ZMC_CALL(NN) main_n<NN>(p, plan, stream)
-    ZMC_BY_DIMS(ZMC_CALL)
+  ZMC_BY_DIMS(ZMC_CALL)
 #undef ZMC_CALL
-  }
-  static hipError_t values(int N, const ScanParams& p, uint64_t g, uint64_t s0, int64_t count,
-                           double* out, hipStream_t stream) {
+}
+
+template <template <typename, int> class F, typename T>
+hipError_t FamilyOps<F, T>::values(int N, const ScanParams& p, uint64_t g, uint64_t s0,
+                                   int64_t count, double* out, hipStream_t stream) {
 #define ZMC_CALL(NN) values_n<NN>(p, g, s0, count, out, stream)
-    ZMC_BY_DIMS(ZMC_CALL)
+  ZMC_BY_DIMS(ZMC_CALL)
 #undef ZMC_CALL
-  }
-  static hipError_t occupancy(int N, int* blocks_per_cu) {
+}
+
+template <template <typename, int> class F, typename T>
+hipError_t FamilyOps<F, T>::occupancy(int N, int* blocks_per_cu) {
 #define ZMC_CALL(NN) occupancy_n<NN>(blocks_per_cu)
-    ZMC_BY_DIMS(ZMC_CALL)
+  ZMC_BY_DIMS(ZMC_CALL)
 #undef ZMC_CALL
-  }
-  static hipError_t batch(int N, const ScanParams* scans, const Tile* tiles, uint32_t begin,
-                          uint32_t end, uint32_t* counter, unsigned blocks, hipStream_t stream) {
+}
+
+template <template <typename, int> class F, typename T>
+hipError_t FamilyOps<F, T>::batch(int N, const ScanParams* scans, const Tile* tiles,
+                                  uint32_t begin, uint32_t end, uint32_t* counter,
+                                  unsigned blocks, hipStream_t stream) {
 #define ZMC_CALL(NN) batch_n<NN>(scans, tiles, begin, end, counter, blocks, stream)
-    ZMC_BY_DIMS(ZMC_CALL)
+  ZMC_BY_DIMS(ZMC_CALL)
 #undef ZMC_CALL
-  }
+}
 #undef ZMC_BY_DIMS
-};
 
 // Launchers of the any-family batch kernel in working precision T.
 template <typename T>
 struct AnyOps {
-  static hipError_t occupancy(int* blocks_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_any<T>, 256, 0);
-  }
+  static hipError_t occupancy(int* blocks_per_cu);
   static hipError_t batch(const ScanParams* scans, const Tile* tiles, uint32_t begin, uint32_t end,
-                          uint32_t* counter, unsigned blocks, hipStream_t stream) {
-    hipLaunchKernelGGL(k_batch_any<T>, dim3(blocks), dim3(256), 0, stream, scans, tiles, begin, end,
-                       counter);
-    return hipGetLastError();
-  }
+                          uint32_t* counter, unsigned blocks, hipStream_t stream);
 };
+
+template <typename T>
+hipError_t AnyOps<T>::occupancy(int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_any<T>, 256, 0);
+}
+
+template <typename T>
+hipError_t AnyOps<T>::batch(const ScanParams* scans, const Tile* tiles, uint32_t begin,
+                            uint32_t end, uint32_t* counter, unsigned blocks, hipStream_t stream) {
+  hipLaunchKernelGGL(k_batch_any<T>, dim3(blocks), dim3(256), 0, stream, scans, tiles, begin, end,
+                     counter);
+  return hipGetLastError();
+}
 
 #define ZMC_DECLARE_FAMILY_OPS(F)                 \
   extern template struct FamilyOps<F, float>;     \
