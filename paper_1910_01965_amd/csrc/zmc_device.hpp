@@ -219,38 +219,21 @@ template <> __device__ __forceinline__ float fmaT(float a, float b, float c) {
 
 constexpr double kLog2e = 1.4426950408889634074;
 
-// FP32 sine and cosine of a phase x through the hardware units, which take
-// their argument in revolutions.  The phase is reduced to [-1/2, 1/2]
-// revolutions with a two-term product by 1/(2 pi) (Cody-Waite style): with
-// r = x c_hi rounded, e = (x c_hi - r) + x c_lo recovered by two fmas, the
-// reduced phase is t = (r - rint(r)) + e, where r - rint(r) is exact; t is
-// off by little more than its own final rounding (2^-25 revolutions at most)
-// for |x| < 2^20.  Larger phases take the library routine.  Six VALU
-// instructions and one transcendental in place of the library's argument
-// reduction and polynomial.
-constexpr float kInv2PiHi = 0.15915494f;                 // float(1/(2 pi))
-constexpr float kInv2PiLo = (float)(0.15915494309189533577 - (double)0.15915494f);
-constexpr float kFastTrigMax = 0x1p20f;
+// FP32 sine and cosine through the hardware units, which take their argument
+// in revolutions.  The FP32 families carry phases in revolutions throughout:
+// the per-point constants are multiplied by 1/(2 pi) in FP64 at set-up, before
+// rounding, so a sample's phase r carries the same relative rounding as the
+// phase in radians would, and r - rint(r) reduces it to [-1/2, 1/2] exactly
+// (for |r| >= 2^23 an FP32 phase no longer resolves a revolution and the
+// reduced phase is 0).
+constexpr double kInv2Pi = 0.15915494309189533577;
 
-__device__ __forceinline__ float reduce_rev(float x) {
-  // no contraction here: fusing r - rint(r) into fma(x, c_hi, -rint(r))
-  // would count the rounding error of r twice
-#pragma clang fp contract(off)
-  const float r = x * kInv2PiHi;
-  const float e = __builtin_fmaf(x, kInv2PiLo, __builtin_fmaf(x, kInv2PiHi, -r));
-  return (r - __builtin_rintf(r)) + e;
+__device__ __forceinline__ float sin_turns(float r) {
+  return __builtin_amdgcn_sinf(r - __builtin_rintf(r));
 }
 
-__device__ __forceinline__ float sin_rev(float x) {
-  float s = __builtin_amdgcn_sinf(reduce_rev(x));
-  if (__builtin_expect(__builtin_fabsf(x) >= kFastTrigMax, 0)) s = sinf(x);
-  return s;
-}
-
-__device__ __forceinline__ float cos_rev(float x) {
-  float c = __builtin_amdgcn_cosf(reduce_rev(x));
-  if (__builtin_expect(__builtin_fabsf(x) >= kFastTrigMax, 0)) c = cosf(x);
-  return c;
+__device__ __forceinline__ float cos_turns(float r) {
+  return __builtin_amdgcn_cosf(r - __builtin_rintf(r));
 }
 
 // Parameter x_l of grid point g (C order: stride_l = prod_{j>l} L_j).
@@ -269,19 +252,20 @@ __device__ __forceinline__ double param_x(const ScanParams& p, uint64_t g, int l
 template <typename T, int N> struct SinSum {
   static constexpr int kMinDims = 1;
   T A[N], B[N];
-  T sx;        // FP64: sum of x; FP32: sum x + sum B folded in
+  T sx;        // FP64: sum of x; FP32: (sum x + sum B) in revolutions
   __device__ void setup(const ScanParams& p, uint64_t g) {
     double s = 0.0, sb = 0.0;
     for (int l = 0; l < p.M; ++l) s += param_x(p, g, l);
+    const double turn = sizeof(T) == 8 ? 1.0 : kInv2Pi;  // FP32: A in revolutions
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       double a, b;
       Unif<T>::affine(p.lo[k], p.hi[k], &a, &b);
-      A[k] = (T)a;
+      A[k] = (T)(a * turn);
       B[k] = (T)b;
       sb += b;
     }
-    sx = sizeof(T) == 8 ? (T)s : (T)(s + sb);
+    sx = sizeof(T) == 8 ? (T)s : (T)((s + sb) * kInv2Pi);
   }
   __device__ __forceinline__ T value(const T* t) const {
     if constexpr (sizeof(T) == 8) {
@@ -293,7 +277,7 @@ template <typename T, int N> struct SinSum {
       float ph = sx;
 #pragma unroll
       for (int k = 0; k < N; ++k) ph = fmaT(A[k], t[k], ph);
-      return sin_rev(ph);
+      return sin_turns(ph);
     }
   }
 };
@@ -377,22 +361,24 @@ template <typename T, int N> struct CosExp {
   T A[N], B[N];
   T x1, x2, nx3sq, x4;  // nx3sq = -x3^2 (FP32: times log2(e))
   T rest;               // FP32: sum of B_k for k >= 3, folded into the phase
+  // FP32: x1, x2, rest and A_k (k >= 3) in revolutions (times 1/(2 pi))
   __device__ void setup(const ScanParams& p, uint64_t g) {
+    const double turn = sizeof(T) == 8 ? 1.0 : kInv2Pi;
     double sb = 0.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       double a, b;
       Unif<T>::affine(p.lo[k], p.hi[k], &a, &b);
-      A[k] = (T)a;
+      A[k] = (T)(k >= 2 ? a * turn : a);
       B[k] = (T)b;
       if (k >= 2) sb += b;
     }
-    x1 = (T)param_x(p, g, 0);
-    x2 = (T)param_x(p, g, 1);
+    x1 = (T)(param_x(p, g, 0) * turn);
+    x2 = (T)(param_x(p, g, 1) * turn);
     const double x3 = param_x(p, g, 2);
     nx3sq = sizeof(T) == 8 ? (T)(-(x3 * x3)) : (T)(-(x3 * x3) * kLog2e);
     x4 = (T)param_x(p, g, 3);
-    rest = (T)sb;
+    rest = (T)(sb * turn);
   }
   __device__ __forceinline__ T value(const T* t) const {
     const T y1 = fmaT(A[0], t[0], B[0]);
@@ -408,7 +394,7 @@ template <typename T, int N> struct CosExp {
       for (int k = 2; k < N; ++k) ph = fmaT(A[k], t[k], ph);
       ph = fmaT(x1, y1, fmaT(x2, y2, ph));
       const float e = __builtin_amdgcn_exp2f(nx3sq * y1 * y2);
-      return fmaT(cos_rev(ph), e, x4);
+      return fmaT(cos_turns(ph), e, x4);
     }
   }
 };
