@@ -4,21 +4,32 @@ TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
 benchmark's CPU-baseline leg; never by the product path.
 
 A scan is described by any object with the attributes
-    family   one of "sin_sum", "gauss", "cosexp", "const", "linear"
+    family   one of "sin_sum", "gauss", "cosexp", "const", "linear", "user"
     axes     sequence of M one-dimensional float64 arrays (parameter lists)
     lo, hi   length-N float64 arrays (the integration box)
     samples  samples per grid point
     seed     Philox key (64 bits)
+    source, params   (family "user") the integrand's source text, which
+             defines template <typename T> T integrand(const T* y, const T* x,
+             const T* p) with __device__ in front, and its constants p
+A user integrand is evaluated by compiling that same text as host C++ with
+g++ (ISO mode, no FMA contraction; <cmath> functions in double), so the GPU
+library and the oracle share the user's text and nothing else.
 This module imports nothing from the GPU package.
 """
 import ctypes
+import hashlib
 import os
+import subprocess
+import tempfile
 
 import numpy as np
 
 from . import build as _build
 
-_FAMILY = {"sin_sum": 0, "gauss": 1, "cosexp": 2, "const": 3, "linear": 4}
+_FAMILY = {"sin_sum": 0, "gauss": 1, "cosexp": 2, "const": 3, "linear": 4, "user": 5}
+_USER_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
 
 
 class _Spec(ctypes.Structure):
@@ -32,10 +43,48 @@ class _Spec(ctypes.Structure):
         ("family", ctypes.c_int32),
         ("samples", ctypes.c_uint64),
         ("seed", ctypes.c_uint64),
+        ("user", _USER_FN),
+        ("params", ctypes.POINTER(ctypes.c_double)),
+        ("n_params", ctypes.c_int32),
     ]
 
 
 _lib = None
+_user_libs = {}
+_user_dir = None
+
+_USER_SHIM = """// host build of a user integrand for the oracle
+#include <cmath>
+using namespace std;
+#define __device__
+#define __host__
+%s
+extern "C" double zmc_oracle_user(const double* y, const double* x, const double* p) {
+  return integrand<double>(y, x, p);
+}
+"""
+
+
+def user_function(source):
+    """The FP64 host function of a user integrand's source (compiled with g++
+    once per source text and process)."""
+    global _user_dir
+    key = hashlib.sha256(source.encode()).hexdigest()[:16]
+    if key not in _user_libs:
+        if _user_dir is None:
+            _user_dir = tempfile.mkdtemp(prefix="zmc_oracle_user_")
+        src = os.path.join(_user_dir, f"user_{key}.cpp")
+        lib = os.path.join(_user_dir, f"user_{key}.so")
+        with open(src, "w") as fh:
+            fh.write(_USER_SHIM % source)
+        r = subprocess.run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                            src, "-o", lib], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise ValueError(f"user integrand does not compile for the oracle:\n{r.stderr}")
+        dll = ctypes.CDLL(lib)
+        fn = _USER_FN(("zmc_oracle_user", dll))
+        _user_libs[key] = (dll, fn)
+    return _user_libs[key][1]
 
 
 def load(path=None):
@@ -79,6 +128,8 @@ class _Marshalled:
         self.axis_vals = (np.concatenate(axes) if axes else np.zeros(1)).astype(np.float64)
         self.lo = np.ascontiguousarray(spec.lo, dtype=np.float64)
         self.hi = np.ascontiguousarray(spec.hi, dtype=np.float64)
+        self.params = np.ascontiguousarray(getattr(spec, "params", np.zeros(0)), dtype=np.float64)
+        user = user_function(spec.source) if spec.family == "user" else _USER_FN()
         self.struct = _Spec(
             M=len(axes),
             N=len(self.lo),
@@ -89,6 +140,9 @@ class _Marshalled:
             family=_FAMILY.get(spec.family, -1),
             samples=int(spec.samples),
             seed=int(spec.seed) & 0xFFFFFFFFFFFFFFFF,
+            user=user,
+            params=self.params.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if self.params.size else None,
+            n_params=int(self.params.size),
         )
 
 
@@ -112,7 +166,8 @@ def word(seed, g, w):
 
 
 def grid_size(spec):
-    return int(load().zmc_oracle_grid_size(ctypes.byref(_Marshalled(spec).struct)))
+    m = _Marshalled(spec)  # owns the arrays the struct points into
+    return int(load().zmc_oracle_grid_size(ctypes.byref(m.struct)))
 
 
 def values(spec, g, s0=0, count=None):
@@ -141,7 +196,7 @@ def scan(spec, idx=None):
     """(f, sigma) float64 arrays at the flat grid indices idx (all points if None)."""
     m = _Marshalled(spec)
     if idx is None:
-        n = grid_size(spec)
+        n = int(load().zmc_oracle_grid_size(ctypes.byref(m.struct)))
         ip = None
     else:
         idx = np.ascontiguousarray(idx, dtype=np.uint64)
