@@ -100,6 +100,11 @@ static int spec_ok(const zmc_oracle_spec* spec) {
     case ZMC_ORACLE_COSEXP: if (spec->M != 4 || spec->N < 2) return 0; break;
     case ZMC_ORACLE_CONST: break;
     case ZMC_ORACLE_LINEAR: break;
+    case ZMC_ORACLE_USER:
+      if (spec->user == NULL) return 0;
+      if (spec->n_params < 0 || spec->n_params > 16) return 0;
+      if (spec->n_params > 0 && spec->params == NULL) return 0;
+      break;
     default: return 0;
   }
   return 1;
@@ -127,10 +132,11 @@ static void decode_point(const zmc_oracle_spec* spec, uint64_t g, double* x) {
 /* ------------------------------------------------------------------------
  * The integrand g(y; x).  y and x are 0-based arrays: y[0] is y_1.
  * ---------------------------------------------------------------------- */
-static double integrand(int family, int M, int N, const double* x,
+static double integrand(const zmc_oracle_spec* spec, const double* x,
                         const double* y) {
+  const int M = spec->M, N = spec->N;
   int k, l;
-  switch (family) {
+  switch (spec->family) {
     case ZMC_ORACLE_SIN_SUM: {
       /* paper Eq. (2) / Eq. (4): sin(sum_j y_j + sum_l x_l) */
       double sx = 0.0, sy = 0.0;
@@ -157,6 +163,11 @@ static double integrand(int family, int M, int N, const double* x,
       double s = 0.0;
       for (k = 0; k < N; ++k) s += y[k];
       return s;
+    }
+    case ZMC_ORACLE_USER: {
+      double p[16];
+      for (k = 0; k < 16; ++k) p[k] = (k < spec->n_params) ? spec->params[k] : 0.0;
+      return spec->user(y, x, p);
     }
     default:
       return NAN;
@@ -202,7 +213,7 @@ int zmc_oracle_values(const zmc_oracle_spec* spec, uint64_t g, uint64_t s0,
       double h = spec->hi[k] - spec->lo[k];
       y[k] = fma(h, u, spec->lo[k]);
     }
-    out[i] = integrand(spec->family, spec->M, spec->N, x, y);
+    out[i] = integrand(spec, x, y);
   }
   return ORACLE_OK;
 }

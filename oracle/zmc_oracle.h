@@ -40,8 +40,14 @@ enum {
   ZMC_ORACLE_COSEXP = 2,  /* cos(x1 y1 + x2 y2 + sum_{k>=3} y_k)
                              * exp(-x3^2 y1 y2) + x4                          */
   ZMC_ORACLE_CONST = 3,   /* 1                                               */
-  ZMC_ORACLE_LINEAR = 4   /* sum_k y_k                                       */
+  ZMC_ORACLE_LINEAR = 4,  /* sum_k y_k                                       */
+  ZMC_ORACLE_USER = 5     /* user(y, x, p): a user-defined integrand         */
 };
+
+/* A user-defined integrand g(y; x) with constants p[0..15] (zero-filled
+ * beyond n_params): the paper's user function of a parameter scan (Sec. 2). */
+typedef double (*zmc_oracle_user_fn)(const double* y, const double* x,
+                                     const double* p);
 
 /* One scan.  All arrays are host memory owned by the caller and read only
  * during a call.  axis_vals holds the M value lists back to back
@@ -56,6 +62,9 @@ typedef struct zmc_oracle_spec {
   int32_t family;           /* ZMC_ORACLE_*                                 */
   uint64_t samples;         /* samples per grid point, >= 2                 */
   uint64_t seed;            /* Philox key                                   */
+  zmc_oracle_user_fn user;  /* ZMC_ORACLE_USER only                         */
+  const double* params;     /* [n_params] constants for `user`              */
+  int32_t n_params;         /* 0..16                                        */
 } zmc_oracle_spec;
 
 /* Return codes: 0 = ok, 1 = invalid spec, 2 = out of memory. */

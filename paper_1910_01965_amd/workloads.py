@@ -21,7 +21,7 @@ from typing import List
 
 import numpy as np
 
-FAMILIES = ("sin_sum", "gauss", "cosexp", "const", "linear")
+FAMILIES = ("sin_sum", "gauss", "cosexp", "const", "linear", "user")
 PRECISIONS = ("fp64", "fp32")
 
 
@@ -36,11 +36,16 @@ class ScanSpec:
     precision: str = "fp64"
     name: str = ""
     meta: dict = field(default_factory=dict)
+    # family "user": the integrand's source text (a function template
+    # integrand<T>(y, x, p), see include/zmc.h) and its constants p
+    source: str = ""
+    params: np.ndarray = field(default_factory=lambda: np.zeros(0))
 
     def __post_init__(self):
         self.axes = [np.ascontiguousarray(a, dtype=np.float64).ravel() for a in self.axes]
         self.lo = np.ascontiguousarray(self.lo, dtype=np.float64).ravel()
         self.hi = np.ascontiguousarray(self.hi, dtype=np.float64).ravel()
+        self.params = np.ascontiguousarray(self.params, dtype=np.float64).ravel()
 
     @property
     def M(self):
@@ -64,7 +69,7 @@ class ScanSpec:
     def with_(self, **kw):
         d = dict(family=self.family, axes=self.axes, lo=self.lo, hi=self.hi,
                  samples=self.samples, seed=self.seed, precision=self.precision,
-                 name=self.name, meta=dict(self.meta))
+                 name=self.name, meta=dict(self.meta), source=self.source, params=self.params)
         d.update(kw)
         return ScanSpec(**d)
 
