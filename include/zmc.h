@@ -58,8 +58,12 @@ typedef enum zmc_family {
   ZMC_COSEXP = 2,  /* cos(x1 y1 + x2 y2 + sum_{k>=3} y_k) exp(-x3^2 y1 y2) + x4,
                       M = 4, N >= 2                                             */
   ZMC_CONST = 3,   /* 1 (sampler and estimator check)                          */
-  ZMC_LINEAR = 4   /* sum_k y_k (sampler and estimator check)                  */
+  ZMC_LINEAR = 4,  /* sum_k y_k (sampler and estimator check)                  */
+  ZMC_USER = 5     /* a user function compiled at run time (zmc_integrand_create),
+                      given by desc->integrand; any M, n_params <= 16          */
 } zmc_family;
+
+typedef struct zmc_integrand zmc_integrand;
 
 typedef enum zmc_precision {
   ZMC_FP64 = 0,         /* FP64 sampling, integrand and accumulation         */
@@ -70,7 +74,8 @@ typedef enum zmc_precision {
 /* One scan.  Limits: 0 <= M <= 16; 1 <= N <= 8 (N <= 16 is a valid
  * descriptor, N > 8 returns ZMC_E_UNSUPPORTED); every axis_len >= 1;
  * G = prod axis_len <= 2^62; lo_k < hi_k, both finite; samples >= 2 and
- * samples * N <= 2^62; n_params = 0 for the five families above. */
+ * samples * N <= 2^62; n_params = 0 for the five compiled-in families,
+ * 0 <= n_params <= 16 for ZMC_USER. */
 typedef struct zmc_scan_desc {
   int32_t M;                /* number of parameters                          */
   int32_t N;                /* integration dimensions                        */
@@ -81,10 +86,12 @@ typedef struct zmc_scan_desc {
   const double* hi;         /* [N] upper box edges                           */
   int32_t family;           /* zmc_family                                    */
   int32_t precision;        /* zmc_precision                                 */
-  const double* params;     /* [n_params] extra family parameters (unused)   */
+  const double* params;     /* [n_params] constants passed to a ZMC_USER
+                               integrand as p[0..n_params-1] (p[i] = 0 beyond) */
   int32_t n_params;
   uint64_t samples;         /* n, samples per grid point                     */
   uint64_t seed;            /* Philox key                                    */
+  const zmc_integrand* integrand;  /* ZMC_USER only (else ignored)           */
 } zmc_scan_desc;
 
 /* Work decomposition.  Zero fields mean "choose automatically".  The results
@@ -167,6 +174,36 @@ zmc_status zmc_debug_words(uint64_t seed, uint64_t g, uint64_t w0, int64_t count
 zmc_status zmc_debug_values(const zmc_scan_desc* desc, const double* d_axis_vals,
                             uint64_t g, uint64_t s0, int64_t count, double* d_out,
                             void* stream);
+
+/* ------------------------------------------------------------------------
+ * User integrands (the paper's user-defined integrand of a parameter scan,
+ * Sec. 2 and Sec. 4, compiled with hipRTC instead of Numba).  `source` is
+ * HIP C++ that defines, at global scope,
+ *
+ *   template <typename T> __device__ T integrand(const T* y, const T* x,
+ *                                                const T* p);
+ *
+ * returning g(y; x) for the sample's coordinates y[0..N-1] in the box, the
+ * grid point's parameters x[0..M-1] and the scan's constants p[0..15]
+ * (desc->params, zero-filled), in the working precision T (double for
+ * ZMC_FP64, float for ZMC_FP32_MERGE64); device math functions (sin, exp,
+ * ...) are available.  The same sampler, accumulators and merges as the
+ * compiled-in families run around it.
+ *
+ * zmc_integrand_create copies the source and compiles one small variant to
+ * report errors (ZMC_E_INVALID with the compiler's log in zmc_last_error);
+ * every (precision, N, M) variant a scan needs is then compiled on first use
+ * (a few seconds) and kept, and loaded once per device.  It needs no GPU.
+ * The handle may be shared by threads; destroy it after its scans finished.
+ * ZMC_USER scans run through zmc_scan, zmc_scan_device(_ex), zmc_plan,
+ * zmc_validate and zmc_debug_values; batches and the server return
+ * ZMC_E_UNSUPPORTED for them. */
+zmc_status zmc_integrand_create(const char* source, zmc_integrand** out);
+
+/* Compiler log of the handle's last build (empty when it produced none). */
+const char* zmc_integrand_log(const zmc_integrand* integrand);
+
+zmc_status zmc_integrand_destroy(zmc_integrand* integrand);
 
 /* ------------------------------------------------------------------------
  * Batched scans.  Many independent scans of uneven grid sizes, sample

@@ -20,11 +20,15 @@ REALS = ("float", "double")
 # translation unit per (family, precision) so that they compile in parallel
 SOURCES = ([("zmc_api.hip", (), "zmc_api"), ("zmc_batch.hip", (), "zmc_batch"),
             ("zmc_tune.hip", (), "zmc_tune"), ("zmc_kernels.hip", (), "zmc_kernels"),
-            ("zmc_server.hip", (), "zmc_server")]
+            ("zmc_server.hip", (), "zmc_server"), ("zmc_rtc.hip", (), "zmc_rtc")]
            + [("zmc_family.hip", (f"-DZMC_FAMILY={f}", f"-DZMC_REAL={r}"), f"zmc_{f}_{r}")
               for f in FAMILIES for r in REALS]
            + [("zmc_any.hip", (f"-DZMC_REAL={r}",), f"zmc_any_{r}") for r in REALS])
 ARCH = "gfx950"
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+# device headers that the run-time compiler of user integrands needs, embedded
+# into the library as text
+RTC_HEADERS = ("zmc_device.hpp", "zmc_scan.hpp", "zmc_user.hpp")
 
 
 def hipcc():
@@ -40,16 +44,35 @@ def flags():
             "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
 
 
+def write_rtc_headers(path):
+    """The device headers as C string literals: kRtcHeaderCount,
+    kRtcHeaderNames[], kRtcHeaderTexts[] (included by zmc_rtc.hip)."""
+    delim = "zmchdr"
+    parts = [f"constexpr int kRtcHeaderCount = {len(RTC_HEADERS)};",
+             "const char* const kRtcHeaderNames[] = {" + ", ".join(f'"{h}"' for h in RTC_HEADERS) + "};",
+             "const char* const kRtcHeaderTexts[] = {"]
+    for h in RTC_HEADERS:
+        text = open(os.path.join(CSRC, h)).read()
+        if f"){delim}\"" in text:
+            raise RuntimeError(f"{h} contains the raw-string delimiter")
+        parts.append(f'R"{delim}({text}){delim}",')
+    parts.append("};")
+    with open(path + ".tmp", "w") as fh:
+        fh.write("\n".join(parts) + "\n")
+    os.replace(path + ".tmp", path)
+
+
 def build(out=LIB, jobs=None, verbose=False):
     """Compile every source and link `out`; returns its path."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     cc = hipcc()
+    write_rtc_headers(os.path.join(objdir, "zmc_rtc_headers.inc"))
 
     def compile_one(entry):
         src, defines, name = entry
         obj = os.path.join(objdir, name + ".o")
-        cmd = [cc, *flags(), *defines, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *flags(), "-I", objdir, *defines, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -62,7 +85,8 @@ def build(out=LIB, jobs=None, verbose=False):
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = out + ".tmp"
-    subprocess.run([cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp], check=True)
+    subprocess.run([cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, f"-L{ROCM}/lib",
+                    "-lhiprtc", f"-Wl,-rpath,{ROCM}/lib", "-o", tmp], check=True)
     os.replace(tmp, out)
     return out
 

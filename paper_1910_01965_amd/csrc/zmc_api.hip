@@ -82,12 +82,23 @@ zmc_status validate(const zmc_scan_desc* d, uint64_t* G_out) {
       if (d->M != 4 || d->N < 2)
         return fail(ZMC_E_INVALID, "COSEXP needs M = 4 and N >= 2 (M = %d, N = %d)", d->M, d->N);
       break;
+    case ZMC_USER:
+      if (d->integrand == nullptr) return fail(ZMC_E_INVALID, "ZMC_USER needs desc->integrand");
+      break;
     default:
       return fail(ZMC_E_INVALID, "unknown family %d", d->family);
   }
   if (d->precision != ZMC_FP64 && d->precision != ZMC_FP32_MERGE64)
     return fail(ZMC_E_INVALID, "unknown precision %d", d->precision);
-  if (d->n_params != 0) return fail(ZMC_E_INVALID, "n_params = %d; these families take none", d->n_params);
+  if (d->family == ZMC_USER) {
+    if (d->n_params < 0 || d->n_params > zmc::kMaxUserParams)
+      return fail(ZMC_E_INVALID, "n_params = %d outside 0..%d", d->n_params, zmc::kMaxUserParams);
+    if (d->n_params > 0 && d->params == nullptr) return fail(ZMC_E_INVALID, "params is NULL with n_params > 0");
+    for (int i = 0; i < d->n_params; ++i)
+      if (!isfinite(d->params[i])) return fail(ZMC_E_INVALID, "params[%d] is not finite", i);
+  } else if (d->n_params != 0) {
+    return fail(ZMC_E_INVALID, "n_params = %d; these families take none", d->n_params);
+  }
   if (d->N > zmc::kMaxDims)
     return fail(ZMC_E_UNSUPPORTED, "N = %d > %d is not built", d->N, zmc::kMaxDims);
   if (G_out) *G_out = G;
@@ -213,6 +224,8 @@ void fill_params(const zmc_scan_desc* d, uint64_t G, const zmc::Plan& pl, const 
     vol *= d->hi[k] - d->lo[k];
   }
   p->vol = vol;
+  p->n_params = d->family == ZMC_USER ? d->n_params : 0;
+  for (int i = 0; i < p->n_params; ++i) p->params[i] = d->params[i];
   p->axis = d_axis;
   p->f = d_f;
   p->sigma = d_sigma;
@@ -277,6 +290,11 @@ zmc_status zmc_scan_device_ex(const zmc_scan_desc* desc, const double* d_axis_va
   zmc::Plan pl;
   st = make_plan(desc, G, opts, &pl);
   if (st != ZMC_OK) return st;
+  zmc::UserKernels uk;
+  if (desc->family == ZMC_USER) {
+    st = zmc::user_kernels(desc->integrand, desc->precision, desc->N, desc->M, &uk);
+    if (st != ZMC_OK) return st;
+  }
   zmc::ScanParams p;
   fill_params(desc, G, pl, d_axis_vals, d_f, d_sigma, &p);
   hipStream_t s = (hipStream_t)stream;
@@ -288,7 +306,8 @@ zmc_status zmc_scan_device_ex(const zmc_scan_desc* desc, const double* d_axis_va
   }
   hipEvent_t ev_b = opts ? (hipEvent_t)opts->ev_begin : nullptr;
   hipEvent_t ev_e = opts ? (hipEvent_t)opts->ev_end : nullptr;
-  hipError_t e = zmc::launch_scan(p, pl, desc->precision, s, ev_b, ev_e);
+  hipError_t e = desc->family == ZMC_USER ? zmc::launch_user_scan(uk, p, pl, s, ev_b, ev_e)
+                                           : zmc::launch_scan(p, pl, desc->precision, s, ev_b, ev_e);
   if (ws != nullptr) {
     hipError_t e2 = hipFreeAsync(ws, s);
     if (e == hipSuccess) e = e2;
@@ -355,9 +374,16 @@ zmc_status zmc_debug_values(const zmc_scan_desc* desc, const double* d_axis_vals
   zmc::Plan pl;
   st = make_plan(desc, G, &o, &pl);
   if (st != ZMC_OK) return st;
+  zmc::UserKernels uk;
+  if (desc->family == ZMC_USER) {
+    st = zmc::user_kernels(desc->integrand, desc->precision, desc->N, desc->M, &uk);
+    if (st != ZMC_OK) return st;
+  }
   zmc::ScanParams p;
   fill_params(desc, G, pl, d_axis_vals, nullptr, nullptr, &p);
-  hipError_t e = zmc::launch_debug_values(p, desc->precision, g, s0, count, d_out, (hipStream_t)stream);
+  hipError_t e = desc->family == ZMC_USER
+                     ? zmc::launch_user_values(uk, p, g, s0, count, d_out, (hipStream_t)stream)
+                     : zmc::launch_debug_values(p, desc->precision, g, s0, count, d_out, (hipStream_t)stream);
   if (e != hipSuccess) return fail(ZMC_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
   return ok();
 }

@@ -130,6 +130,8 @@ zmc_status plan_batch(const zmc_scan_desc* scans, int32_t n, const zmc_batch_opt
       snprintf(why, sizeof(why), "%s", zmc_last_error());
       return fail(st, "scan %d: %s", i, why);
     }
+    if (scans[i].family == ZMC_USER)
+      return fail(ZMC_E_UNSUPPORTED, "scan %d: user integrands run through the single-scan entry points", i);
     ScanPlanB& sp = bp->scans[(size_t)i];
     st = plan_scan(&scans[i], G, o, &sp);
     if (st != ZMC_OK) return st;

@@ -7,8 +7,17 @@
 // estimate open, and the library fixes them as stated in include/zmc.h.
 #pragma once
 
+#if defined(__HIPCC_RTC__)
+// hipRTC (user integrands): its runtime header keeps the fixed-width types
+// in its own namespace
+using __hip_internal::int32_t;
+using __hip_internal::int64_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
+#else
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 #include <type_traits>
 
@@ -16,6 +25,7 @@ namespace zmc {
 
 constexpr int kMaxParams = 16;
 constexpr int kMaxDims = 8;
+constexpr int kMaxUserParams = 16;  // constants passed to a user integrand
 
 // Everything a scan kernel needs, passed by value as the kernel argument.
 struct ScanParams {
@@ -27,12 +37,13 @@ struct ScanParams {
   uint64_t point_blocks; // ceil(G / block) (point-major)
   int32_t M, N, splits, family;
   int32_t fast_counter;  // 1 when every word block b and grid index g is < 2^32
-  int32_t pad_;
+  int32_t n_params;      // user integrands: entries of params in use
   int64_t axis_len[kMaxParams];
   int64_t axis_off[kMaxParams];
   uint64_t axis_stride[kMaxParams];  // prod of the lengths of later axes
   double lo[kMaxDims], hi[kMaxDims];
   double vol;
+  double params[kMaxUserParams];
   const double* axis;    // device: concatenated value lists
   double* f;             // device outputs [G]
   double* sigma;

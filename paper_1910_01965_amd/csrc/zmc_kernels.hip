@@ -68,6 +68,10 @@ hipError_t launch_scan(const ScanParams& p, const Plan& plan, int precision, hip
     e = by_precision(precision, p.family, [&](auto ops) { return ops.main(p.N, p, plan, stream); });
   if (e == hipSuccess && ev_end != nullptr) e = hipEventRecord(ev_end, stream);
   if (e != hipSuccess || p.splits == 1) return e;
+  return launch_merge_splits(p, stream);
+}
+
+hipError_t launch_merge_splits(const ScanParams& p, hipStream_t stream) {
   uint64_t blocks = (p.G + 255) / 256;
   if (blocks > (1u << 20)) blocks = 1u << 20;
   hipLaunchKernelGGL(k_merge_splits, dim3((unsigned)blocks), dim3(256), 0, stream, p);

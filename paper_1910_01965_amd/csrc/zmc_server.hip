@@ -454,6 +454,8 @@ zmc_status zmc_server_submit(zmc_server* s, const zmc_scan_desc* desc, const dou
   uint64_t G = 0;
   zmc_status st = zmc::validate_desc(desc, &G);
   if (st != ZMC_OK) return st;
+  if (desc->family == ZMC_USER)
+    return fail(ZMC_E_UNSUPPORTED, "user integrands run through the single-scan entry points");
   if (d_f == nullptr || d_sigma == nullptr) return fail(ZMC_E_INVALID, "d_f or d_sigma is NULL");
   if (desc->M > 0 && d_axis_vals == nullptr && desc->axis_vals == nullptr)
     return fail(ZMC_E_INVALID, "no parameter lists (host or device)");

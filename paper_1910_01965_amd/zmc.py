@@ -13,7 +13,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzmc.so")
 
-FAMILY = {"sin_sum": 0, "gauss": 1, "cosexp": 2, "const": 3, "linear": 4}
+FAMILY = {"sin_sum": 0, "gauss": 1, "cosexp": 2, "const": 3, "linear": 4, "user": 5}
 PRECISION = {"fp64": 0, "fp32": 1}
 MODE = {"auto": 0, "point_major": 1, "sample_major": 2}
 MODE_NAME = {v: k for k, v in MODE.items()}
@@ -25,7 +25,8 @@ EXPORTS = ("zmc_last_error", "zmc_version", "zmc_validate", "zmc_plan", "zmc_sca
            "zmc_batch_default_opts", "zmc_batch_plan", "zmc_batch_create", "zmc_batch_launch",
            "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch", "zmc_tune_source",
            "zmc_server_create", "zmc_server_submit", "zmc_server_poll", "zmc_server_wait",
-           "zmc_server_get_stats", "zmc_server_destroy")
+           "zmc_server_get_stats", "zmc_server_destroy", "zmc_integrand_create",
+           "zmc_integrand_log", "zmc_integrand_destroy")
 
 
 class ZmcError(RuntimeError):
@@ -48,6 +49,7 @@ class ScanDesc(ctypes.Structure):
         ("n_params", ctypes.c_int32),
         ("samples", ctypes.c_uint64),
         ("seed", ctypes.c_uint64),
+        ("integrand", ctypes.c_void_p),
     ]
 
 
@@ -137,7 +139,11 @@ def load():
                                         ctypes.POINTER(ctypes.c_double)]
         lib.zmc_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
         lib.zmc_server_destroy.argtypes = [vp]
-        for name in ("zmc_validate", "zmc_plan", "zmc_scan", "zmc_scan_device",
+        lib.zmc_integrand_create.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+        lib.zmc_integrand_log.argtypes = [vp]
+        lib.zmc_integrand_log.restype = ctypes.c_char_p
+        lib.zmc_integrand_destroy.argtypes = [vp]
+        for name in ("zmc_integrand_create", "zmc_integrand_destroy", "zmc_validate", "zmc_plan", "zmc_scan", "zmc_scan_device",
                      "zmc_scan_device_ex", "zmc_debug_words", "zmc_debug_values",
                      "zmc_batch_plan", "zmc_batch_create", "zmc_batch_launch",
                      "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch",
@@ -153,6 +159,48 @@ def _check(status):
         raise ZmcError(status, load().zmc_last_error().decode())
 
 
+class Integrand:
+    """A user integrand compiled at run time (zmc_integrand_create): `source`
+    defines template <typename T> __device__ T integrand(const T* y,
+    const T* x, const T* p).  Raises ZmcError (with the compiler's log) when
+    it does not compile."""
+
+    def __init__(self, source):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.zmc_integrand_create(source.encode(), ctypes.byref(h)))
+        self.source = source
+        self.handle = h.value
+        self._lib = lib
+
+    def log(self):
+        return self._lib.zmc_integrand_log(ctypes.c_void_p(self.handle)).decode()
+
+    def close(self):
+        if self.handle:
+            _check(self._lib.zmc_integrand_destroy(ctypes.c_void_p(self.handle)))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_integrands = {}
+
+
+def integrand(source):
+    """The process-wide Integrand for `source` (compiled once)."""
+    if not source:
+        raise ZmcError(1, "family 'user' needs ScanSpec.source")
+    it = _integrands.get(source)
+    if it is None:
+        it = _integrands[source] = Integrand(source)
+    return it
+
+
 class Desc:
     """A C descriptor for one ScanSpec; keeps its host arrays alive."""
 
@@ -163,6 +211,8 @@ class Desc:
         self.lo = np.ascontiguousarray(spec.lo, dtype=np.float64)
         self.hi = np.ascontiguousarray(spec.hi, dtype=np.float64)
         prec = precision or spec.precision
+        self.params = np.ascontiguousarray(getattr(spec, "params", np.zeros(0)), dtype=np.float64)
+        self.integrand = integrand(spec.source) if spec.family == "user" else None
         self.c = ScanDesc(
             M=len(spec.axes), N=len(self.lo),
             axis_len=self.axis_len.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
@@ -170,8 +220,10 @@ class Desc:
             lo=self.lo.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
             hi=self.hi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
             family=FAMILY.get(spec.family, -1), precision=PRECISION.get(prec, -1),
-            params=None, n_params=0, samples=int(spec.samples),
-            seed=int(spec.seed) & 0xFFFFFFFFFFFFFFFF)
+            params=self.params.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if self.params.size else None,
+            n_params=int(self.params.size), samples=int(spec.samples),
+            seed=int(spec.seed) & 0xFFFFFFFFFFFFFFFF,
+            integrand=self.integrand.handle if self.integrand is not None else None)
 
     @property
     def ref(self):

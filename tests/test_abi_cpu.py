@@ -147,3 +147,55 @@ def test_batch_plan_names_the_bad_scan(lib):
     assert ei.value.status == 1 and "scan 3" in str(ei.value)
     with pytest.raises(zmc.ZmcError):
         zmc.batch_plan([], cu_count=256)
+
+
+USER_SRC = ("template <typename T> __device__ T integrand(const T* y, const T* x, const T* p) {\n"
+            "  return sin(x[0] * y[0]) * exp(-p[0] * y[1] * y[1]) + p[1];\n}\n")
+
+
+def test_user_integrand_compiles_without_a_gpu(lib):
+    it = zmc.Integrand(USER_SRC)
+    assert it.handle
+    spec = wl.ScanSpec("user", [np.linspace(0, 1, 5)], np.zeros(2), np.ones(2), 100, 3, "fp32",
+                       source=USER_SRC, params=np.array([0.5, 2.0]))
+    assert zmc.validate(spec) == 5
+    it.close()
+
+
+def test_user_integrand_compile_error_is_reported(lib):
+    bad = USER_SRC.replace("exp(", "no_such_function(")
+    with pytest.raises(zmc.ZmcError) as ei:
+        zmc.Integrand(bad)
+    assert ei.value.status == 1 and "no_such_function" in str(ei.value)
+    with pytest.raises(zmc.ZmcError):
+        zmc.Integrand("")
+
+
+def test_user_descriptor_validation(lib):
+    spec = wl.ScanSpec("user", [np.linspace(0, 1, 5)], np.zeros(2), np.ones(2), 100, 3,
+                       source=USER_SRC, params=np.zeros(17))
+    with pytest.raises(zmc.ZmcError) as ei:
+        zmc.validate(spec)                        # more than 16 constants
+    assert ei.value.status == 1
+    with pytest.raises(zmc.ZmcError):
+        zmc.validate(spec.with_(params=np.array([np.inf])))
+    d = zmc.Desc(spec.with_(params=np.zeros(2)))
+    d.c.integrand = None                          # ZMC_USER without a handle
+    G = ctypes_u64()
+    assert lib.zmc_validate(d.ref, G) == 1
+    # built-in families take no constants
+    with pytest.raises(zmc.ZmcError):
+        zmc.validate(GOOD.with_(params=np.ones(1)))
+
+
+def test_user_scans_are_not_batched(lib):
+    spec = wl.ScanSpec("user", [np.linspace(0, 1, 5)], np.zeros(2), np.ones(2), 100, 3,
+                       source=USER_SRC, params=np.array([0.5, 2.0]))
+    with pytest.raises(zmc.ZmcError) as ei:
+        zmc.batch_plan([GOOD, spec], cu_count=256)
+    assert ei.value.status == 4 and "scan 1" in str(ei.value)
+
+
+def ctypes_u64():
+    import ctypes
+    return ctypes.byref(ctypes.c_uint64())
