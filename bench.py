@@ -195,6 +195,34 @@ def copy_probe(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
 
 
+USER_GAUSS = ("template <typename T> __device__ T integrand(const T* y, const T* x, const T* p) {\n"
+              "  return exp(-(x[0] * y[0] * y[0] + x[1] * y[1] * y[1] + y[2] * y[2]));\n}\n")
+
+
+def user_run(spec, out):
+    """The Gaussian bench workload as a run-time-compiled user integrand (the
+    integrand written plainly, as a user would), FP32 and FP64, beside the
+    compiled-in family; plus the one-time compile and load cost."""
+    import torch
+    from paper_1910_01965_amd import zmc
+    res = {"source": USER_GAUSS}
+    for prec, steps, ref in (("fp32", 5, out["value"]), ("fp64", 2, out["fp64"]["value"])):
+        sp = spec.with_(family="user", source=USER_GAUSS, precision=prec, name=spec.name + "_user")
+        t0 = time.perf_counter()
+        zmc.integrand(USER_GAUSS)
+        f, s = zmc.scan(sp.with_(axes=[a[:2] for a in sp.axes], samples=64))  # compiles (prec, N, M)
+        torch.cuda.synchronize()
+        first = time.perf_counter() - t0
+        log(f"config user gauss {prec}: first use (compile + load) {first:.2f} s, {steps} steps")
+        r = time_path(sp, steps, 1)
+        ms = r["wall_s"] * 1e3 / steps
+        v = sp.G * sp.samples / (ms / 1e3)
+        res[prec] = {"samples_per_s": v, "ms_per_step": ms, "kernel_ms": float(np.mean(r["kernel_ms"])),
+                     "vs_compiled_family": v / ref, "first_use_s": first}
+        log(f"  {v:.4g} samples/s ({v / ref:.3f}x the compiled-in family)")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,6 +311,7 @@ def main():
                 "ms_per_step": ms, "kernel_ms": km, "plan": r["plan"],
                 "valu_frac": w * sp.G * sp.samples / (km / 1e3) / VALU_PEAK if sp.precision == "fp32" else None}
             log(f"  {out['configs'][name]['samples_per_s']:.4g} samples/s, {ms:.3f} ms/step")
+        out["configs"]["user_gauss_2p_1000x1000_n16384"] = user_run(spec, out)
     if not args.no_batched:
         log("batched: 512 scans")
         out["batched"] = batched_run()
