@@ -223,6 +223,56 @@ def user_run(spec, out):
     return res
 
 
+def chunked_run(big=False):
+    """Out-of-core scans into host memory.  The Boltzmann-shaped grid of the
+    paper's Sec. 3.3 (momentum 30^3 x 10^3 values x 7 species = 1.89e8 points,
+    a 5-dimensional integral; SIN_SUM over seven parameters stands in for the
+    collision integrand, which the paper does not give), 1024 samples, FP32:
+    device-only scan vs chunked into pageable and into pinned host arrays.
+    `big`: a 2.1e9-point grid (34 GB of f and sigma) streamed in 2^24-point
+    chunks."""
+    import torch
+    from paper_1910_01965_amd import workloads as wl
+    from paper_1910_01965_amd import zmc
+    axes = [np.linspace(0.0, 1.0, 30)] * 3 + [np.linspace(0.0, 0.5, 10)] * 3 + [np.arange(7.0)]
+    spec = wl.ScanSpec("sin_sum", axes, np.zeros(5), np.ones(5), 1024, 5, "fp32",
+                       name="boltzmann_shape_30^3x10^3x7_N5_n1024")
+    res = {"workload": spec.name, "grid_points": spec.G, "samples_per_point": spec.samples}
+    r = time_path(spec, 2, 1)
+    dev = r["wall_s"] / 2
+    res["device_only_s"] = dev
+    f = np.zeros(spec.G)
+    s = np.zeros(spec.G)
+    zmc.scan_chunked(spec, 0, f, s)
+    t0 = time.perf_counter()
+    zmc.scan_chunked(spec, 0, f, s)
+    res["chunked_pageable_s"] = time.perf_counter() - t0
+    del f, s
+    fp = torch.empty(spec.G, dtype=torch.float64, pin_memory=True)
+    sp = torch.empty(spec.G, dtype=torch.float64, pin_memory=True)
+    t0 = time.perf_counter()
+    zmc.scan_chunked(spec, 0, fp, sp)
+    res["chunked_pinned_s"] = time.perf_counter() - t0
+    del fp, sp
+    for k in ("device_only_s", "chunked_pageable_s", "chunked_pinned_s"):
+        res[k.replace("_s", "_pts_per_s")] = spec.G / res[k]
+    log(f"chunked {spec.name}: device {dev:.3f} s, pageable {res['chunked_pageable_s']:.3f} s, "
+        f"pinned {res['chunked_pinned_s']:.3f} s")
+    if big:
+        bspec = wl.ScanSpec("sin_sum", [np.linspace(0, 1, 2048), np.linspace(0, 1, 1024),
+                                        np.linspace(0, 1, 1024)], np.zeros(2), np.ones(2), 16, 6, "fp32",
+                            name="grid_2048x1024x1024_N2_n16")
+        f = np.zeros(bspec.G)
+        s = np.zeros(bspec.G)
+        t0 = time.perf_counter()
+        zmc.scan_chunked(bspec, 0, f, s)
+        tb = time.perf_counter() - t0
+        res["big"] = {"workload": bspec.name, "grid_points": bspec.G, "host_bytes": 16 * bspec.G,
+                      "seconds": tb, "pts_per_s": bspec.G / tb, "finite": bool(np.isfinite(f).all())}
+        log(f"chunked {bspec.name}: {tb:.2f} s for {bspec.G} points")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,6 +284,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-chunked", action="store_true")
+    ap.add_argument("--chunked-big", action="store_true",
+                    help="also stream a 2.1e9-point grid (34 GB of host memory)")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="arrival window of the serving runs (the full workload is 60 s)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -312,6 +365,8 @@ def main():
                 "valu_frac": w * sp.G * sp.samples / (km / 1e3) / VALU_PEAK if sp.precision == "fp32" else None}
             log(f"  {out['configs'][name]['samples_per_s']:.4g} samples/s, {ms:.3f} ms/step")
         out["configs"]["user_gauss_2p_1000x1000_n16384"] = user_run(spec, out)
+    if not args.no_chunked:
+        out["chunked"] = chunked_run(args.chunked_big)
     if not args.no_batched:
         log("batched: 512 scans")
         out["batched"] = batched_run()

@@ -158,6 +158,18 @@ zmc_status zmc_scan(const zmc_scan_desc* desc, double* f, double* sigma);
 zmc_status zmc_scan_device(const zmc_scan_desc* desc, const double* d_axis_vals,
                            double* d_f, double* d_sigma, void* stream);
 
+/* Out-of-core scan into host memory, for grids whose f and sigma do not
+ * fit on the device (the paper's scale claim, Sec. 1 and Sec. 3.3): the grid
+ * runs as consecutive chunks of chunk_points points (0 = 2^24), each with
+ * the decomposition of the whole grid, so the results equal those of one
+ * scan of the whole grid bit for bit.  While the device computes chunk i,
+ * chunk i-1 is copied back over PCIe and, when f and sigma are pageable,
+ * from pinned staging into them on host threads; outputs in pinned memory
+ * (hipHostMalloc) take the copies directly.  Device memory: the lists plus
+ * 2 x 16 B x chunk_points plus the chunk's split partials.  Synchronous. */
+zmc_status zmc_scan_chunked(const zmc_scan_desc* desc, double* f, double* sigma,
+                            uint64_t chunk_points);
+
 /* zmc_scan_device with an explicit decomposition (opts may be NULL). */
 zmc_status zmc_scan_device_ex(const zmc_scan_desc* desc, const double* d_axis_vals,
                               double* d_f, double* d_sigma,

@@ -5,7 +5,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "zmc.h"
@@ -139,6 +141,8 @@ uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 constexpr uint64_t kMaxGridX = (uint64_t)1 << 30;
 constexpr int kMaxSplits = 65535;
 constexpr uint64_t kMaxWorkspace = (uint64_t)8 << 30;
+constexpr uint64_t kDefaultChunk = (uint64_t)1 << 24;  // points per chunk of a chunked scan
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 zmc_status make_plan(const zmc_scan_desc* d, uint64_t G, const zmc_launch_opts* o, zmc::Plan* pl) {
   int cu = (o && o->cu_count > 0) ? o->cu_count : 0;
@@ -193,9 +197,10 @@ zmc_status make_plan(const zmc_scan_desc* d, uint64_t G, const zmc_launch_opts* 
 }
 
 void fill_params(const zmc_scan_desc* d, uint64_t G, const zmc::Plan& pl, const double* d_axis,
-                 double* d_f, double* d_sigma, zmc::ScanParams* p) {
+                 double* d_f, double* d_sigma, zmc::ScanParams* p, uint64_t g_base = 0) {
   memset(p, 0, sizeof(*p));
   p->G = G;
+  p->g_base = g_base;
   p->n = d->samples;
   p->n_groups = pl.groups;
   p->gps = pl.gps;
@@ -205,7 +210,8 @@ void fill_params(const zmc_scan_desc* d, uint64_t G, const zmc::Plan& pl, const 
   p->N = d->N;
   p->splits = pl.splits;
   p->family = d->family;
-  p->fast_counter = (G <= ((uint64_t)1 << 32) && pl.groups * (uint64_t)d->N <= ((uint64_t)1 << 32)) ? 1 : 0;
+  p->fast_counter =
+      (g_base + G <= ((uint64_t)1 << 32) && pl.groups * (uint64_t)d->N <= ((uint64_t)1 << 32)) ? 1 : 0;
   int64_t off = 0;
   uint64_t stride = 1;
   for (int l = d->M - 1; l >= 0; --l) {
@@ -385,6 +391,129 @@ zmc_status zmc_debug_values(const zmc_scan_desc* desc, const double* d_axis_vals
                      ? zmc::launch_user_values(uk, p, g, s0, count, d_out, (hipStream_t)stream)
                      : zmc::launch_debug_values(p, desc->precision, g, s0, count, d_out, (hipStream_t)stream);
   if (e != hipSuccess) return fail(ZMC_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+
+zmc_status zmc_scan_chunked(const zmc_scan_desc* desc, double* f, double* sigma,
+                            uint64_t chunk_points) {
+  uint64_t G = 0;
+  zmc_status st = validate(desc, &G);
+  if (st != ZMC_OK) return st;
+  if (desc->M > 0 && desc->axis_vals == nullptr) return fail(ZMC_E_INVALID, "axis_vals is NULL with M > 0");
+  if (f == nullptr || sigma == nullptr) return fail(ZMC_E_INVALID, "f or sigma is NULL");
+  zmc::UserKernels uk;
+  if (desc->family == ZMC_USER) {
+    st = zmc::user_kernels(desc->integrand, desc->precision, desc->N, desc->M, &uk);
+    if (st != ZMC_OK) return st;
+  }
+  // every chunk runs the decomposition of the whole grid, so its points get
+  // the same sample pieces (and results) as in a scan of the whole grid
+  zmc::Plan full;
+  st = make_plan(desc, G, nullptr, &full);
+  if (st != ZMC_OK) return st;
+  const zmc_launch_opts fixed{full.mode, full.block, full.splits, 0, nullptr, nullptr};
+  const uint64_t C = std::min<uint64_t>(G, chunk_points > 0 ? chunk_points : kDefaultChunk);
+  zmc::Plan cp;
+  st = make_plan(desc, C, &fixed, &cp);
+  if (st != ZMC_OK) return st;
+  if ((uint64_t)cp.splits != (uint64_t)full.splits || cp.gps != full.gps)
+    return fail(ZMC_E_INVALID, "chunk plan differs from the grid's plan");
+
+  uint64_t n_axis = 0;
+  for (int l = 0; l < desc->M; ++l) n_axis += (uint64_t)desc->axis_len[l];
+  const size_t off_out = align256(8 * n_axis);
+  const size_t slot_bytes = align256(16 * C);   // f then sigma of one chunk
+  const size_t off_ws = off_out + 2 * slot_bytes;
+  const size_t total = off_ws + cp.workspace_bytes;
+  // outputs already in pinned host memory take the copies directly
+  bool pinned = true;
+  for (double* ptr : {f, sigma}) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, ptr) != hipSuccess || a.type != hipMemoryTypeHost) pinned = false;
+  }
+  (void)hipGetLastError();  // pageable memory can leave an error behind
+
+  char* dmem = nullptr;
+  double* stage = nullptr;
+  hipStream_t streams[2] = {nullptr, nullptr};
+  hipEvent_t computed[2] = {nullptr, nullptr}, copied[2] = {nullptr, nullptr};
+  hipError_t e = hipMalloc((void**)&dmem, total);
+  if (e == hipSuccess && !pinned) e = hipHostMalloc((void**)&stage, 2 * 16 * C, 0);
+  for (int i = 0; e == hipSuccess && i < 2; ++i) e = hipStreamCreateWithFlags(&streams[i], hipStreamNonBlocking);
+  for (int i = 0; e == hipSuccess && i < 2; ++i) {
+    e = hipEventCreateWithFlags(&computed[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&copied[i], hipEventDisableTiming);
+  }
+  if (e == hipSuccess && n_axis > 0) e = hipMemcpy(dmem, desc->axis_vals, 8 * n_axis, hipMemcpyHostToDevice);
+  const double* d_axis = (const double*)dmem;
+  auto host_copy = [&](int slot, uint64_t g0, uint64_t n) {
+    // pinned staging -> the caller's arrays, on a few host threads
+    const double* src = stage + (size_t)slot * 2 * C;
+    const uint64_t parts = n >= ((uint64_t)1 << 20) ? 4 : 1;
+    std::vector<std::thread> th;
+    for (uint64_t t = 0; t < parts; ++t) {
+      const uint64_t a = n * t / parts, b = n * (t + 1) / parts;
+      th.emplace_back([=] {
+        memcpy(f + g0 + a, src + a, 8 * (b - a));
+        memcpy(sigma + g0 + a, src + C + a, 8 * (b - a));
+      });
+    }
+    for (auto& x : th) x.join();
+  };
+  const uint64_t chunks = (G + C - 1) / C;
+  uint64_t prev_g0 = 0, prev_n = 0;
+  for (uint64_t i = 0; e == hipSuccess && i < chunks; ++i) {
+    const int slot = (int)(i & 1);
+    const uint64_t g0 = i * C, n = std::min<uint64_t>(C, G - g0);
+    double* d_f = (double*)(dmem + off_out + (size_t)slot * slot_bytes);
+    double* d_s = d_f + C;
+    zmc::Plan pl;
+    st = make_plan(desc, n, &fixed, &pl);
+    if (st != ZMC_OK) break;
+    zmc::ScanParams p;
+    fill_params(desc, n, pl, d_axis, d_f, d_s, &p, g0);
+    if (pl.workspace_bytes > 0) {
+      p.part_mean = (double*)(dmem + off_ws);
+      p.part_m2 = p.part_mean + (uint64_t)pl.splits * n;
+    }
+    // the device slot is free once chunk i-2 has been copied out of it
+    if (i >= 2) e = hipStreamWaitEvent(streams[0], copied[slot], 0);
+    if (e == hipSuccess)
+      e = desc->family == ZMC_USER ? zmc::launch_user_scan(uk, p, pl, streams[0], nullptr, nullptr)
+                                   : zmc::launch_scan(p, pl, desc->precision, streams[0], nullptr, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(computed[slot], streams[0]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(streams[1], computed[slot], 0);
+    double* h_f = pinned ? f + g0 : stage + (size_t)slot * 2 * C;
+    double* h_s = pinned ? sigma + g0 : stage + (size_t)slot * 2 * C + C;
+    if (e == hipSuccess) e = hipMemcpyAsync(h_f, d_f, 8 * n, hipMemcpyDeviceToHost, streams[1]);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_s, d_s, 8 * n, hipMemcpyDeviceToHost, streams[1]);
+    if (e == hipSuccess) e = hipEventRecord(copied[slot], streams[1]);
+    // while the device works on chunk i, the host stores chunk i-1
+    if (e == hipSuccess && i >= 1 && !pinned) {
+      e = hipEventSynchronize(copied[slot ^ 1]);
+      if (e == hipSuccess) host_copy(slot ^ 1, prev_g0, prev_n);
+    }
+    prev_g0 = g0;
+    prev_n = n;
+  }
+  if (e == hipSuccess && st == ZMC_OK && chunks > 0) {
+    e = hipEventSynchronize(copied[(chunks - 1) & 1]);
+    if (e == hipSuccess && !pinned) host_copy((int)((chunks - 1) & 1), prev_g0, prev_n);
+  }
+  for (int i = 0; i < 2; ++i)
+    if (streams[i]) (void)hipStreamSynchronize(streams[i]);
+  for (int i = 0; i < 2; ++i) {
+    if (computed[i]) (void)hipEventDestroy(computed[i]);
+    if (copied[i]) (void)hipEventDestroy(copied[i]);
+    if (streams[i]) (void)hipStreamDestroy(streams[i]);
+  }
+  if (stage) (void)hipHostFree(stage);
+  if (dmem) (void)hipFree(dmem);
+  if (st != ZMC_OK) return st;
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? ZMC_E_NOMEM : ZMC_E_DEVICE, "chunked scan failed: %s",
+                hipGetErrorString(e));
   return ok();
 }
 

@@ -29,14 +29,15 @@ constexpr int kMaxUserParams = 16;  // constants passed to a user integrand
 
 // Everything a scan kernel needs, passed by value as the kernel argument.
 struct ScanParams {
-  uint64_t G;            // grid points
+  uint64_t G;            // grid points of this launch (local indices 0..G-1)
+  uint64_t g_base;       // global flat index of local point 0 (chunked scans)
   uint64_t n;            // samples per point
   uint64_t n_groups;     // ceil(n / 4)
   uint64_t gps;          // groups per split
   uint64_t seed;
   uint64_t point_blocks; // ceil(G / block) (point-major)
   int32_t M, N, splits, family;
-  int32_t fast_counter;  // 1 when every word block b and grid index g is < 2^32
+  int32_t fast_counter;  // 1 when every word block b and global index g is < 2^32
   int32_t n_params;      // user integrands: entries of params in use
   int64_t axis_len[kMaxParams];
   int64_t axis_off[kMaxParams];

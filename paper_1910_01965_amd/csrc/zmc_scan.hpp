@@ -62,19 +62,20 @@ __device__ __forceinline__ void pm_tile(const ScanParams& p, uint64_t first, uin
   const bool ragged = (j1 == p.n_groups) && ((p.n & 3u) != 0);
   const uint64_t jfull = ragged ? j1 - 1 : j1;
   const int tail = (int)(p.n - 4 * (p.n_groups - 1));
-  const uint64_t g = first + threadIdx.x;
+  const uint64_t g = first + threadIdx.x;  // local index: outputs
   if (g >= p.G) return;
+  const uint64_t gg = p.g_base + g;        // global index: parameters and stream
   Fam fam;
-  fam.setup(p, g);
+  fam.setup(p, gg);
   LaneAcc<T> acc;
   acc.init((T)0);
   with_form(fam, [&](const auto& f) {
     using F = std::decay_t<decltype(f)>;
     if (p.fast_counter) {
-      const GenPointMajor gen{philox_lane((uint32_t)g, p.seed)};
+      const GenPointMajor gen{philox_lane((uint32_t)gg, p.seed)};
       lane_groups<F, T, N>(f, gen, j0, jfull, ragged, tail, acc);
     } else {
-      const GenAny gen{g, p.seed};
+      const GenAny gen{gg, p.seed};
       lane_groups<F, T, N>(f, gen, j0, jfull, ragged, tail, acc);
     }
   });
@@ -87,10 +88,10 @@ __device__ __forceinline__ void pm_tile(const ScanParams& p, uint64_t first, uin
   }
 }
 
-// One sample-major tile: the whole block works on grid point g over sample
-// piece sp (lane t takes groups j0 + t, j0 + t + T, ...), then merges its
-// lanes.  Every thread of the block must call it (it synchronises); `lds`
-// holds 3 x 16 doubles.
+// One sample-major tile: the whole block works on grid point g (local index;
+// its global index is p.g_base + g) over sample piece sp (lane t takes
+// groups j0 + t, j0 + t + T, ...), then merges its lanes.  Every thread of
+// the block must call it (it synchronises); `lds` holds 3 x 16 doubles.
 template <class Fam, typename T, int N>
 __device__ __forceinline__ void sm_tile(const ScanParams& p, uint64_t g, uint64_t sp, double* lds) {
   const uint64_t j0 = sp * p.gps;
@@ -99,11 +100,11 @@ __device__ __forceinline__ void sm_tile(const ScanParams& p, uint64_t g, uint64_
   const int tail = (int)(p.n - 4 * last);  // samples in the scan's last group
   const unsigned waves = blockDim.x >> 6;
   Fam fam;
-  fam.setup(p, g);
+  fam.setup(p, p.g_base + g);
   LaneAcc<T> acc;
   acc.init((T)0);
   double count = 0.0;
-  const GenAny gen{g, p.seed};
+  const GenAny gen{p.g_base + g, p.seed};
   with_form(fam, [&](const auto& f) {
     using F = std::decay_t<decltype(f)>;
     for (uint64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
@@ -153,7 +154,8 @@ __device__ __forceinline__ void merge_point(const ScanParams& p, uint64_t g) {
 
 // Kernel bodies: the point-major scan (grid.x = point blocks, grid.y = sample
 // pieces), the sample-major scan (grid.x = points, grid.y = pieces; `lds`
-// holds 3 x 16 doubles) and per-sample integrand values (debugging, parity).
+// holds 3 x 16 doubles) and per-sample integrand values of global point g
+// (debugging, parity).
 template <class Fam, typename T, int N>
 __device__ __forceinline__ void point_major_body(const ScanParams& p) {
   for (uint64_t pb = blockIdx.x; pb < p.point_blocks; pb += gridDim.x)

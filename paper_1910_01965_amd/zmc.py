@@ -26,7 +26,7 @@ EXPORTS = ("zmc_last_error", "zmc_version", "zmc_validate", "zmc_plan", "zmc_sca
            "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch", "zmc_tune_source",
            "zmc_server_create", "zmc_server_submit", "zmc_server_poll", "zmc_server_wait",
            "zmc_server_get_stats", "zmc_server_destroy", "zmc_integrand_create",
-           "zmc_integrand_log", "zmc_integrand_destroy")
+           "zmc_integrand_log", "zmc_integrand_destroy", "zmc_scan_chunked")
 
 
 class ZmcError(RuntimeError):
@@ -112,6 +112,7 @@ def load():
         lib.zmc_validate.argtypes = [descp, ctypes.POINTER(ctypes.c_uint64)]
         lib.zmc_plan.argtypes = [descp, ctypes.POINTER(LaunchOpts), ctypes.POINTER(PlanInfo)]
         lib.zmc_scan.argtypes = [descp, dp, dp]
+        lib.zmc_scan_chunked.argtypes = [descp, vp, vp, ctypes.c_uint64]
         lib.zmc_scan_device.argtypes = [descp, vp, vp, vp, vp]
         lib.zmc_scan_device_ex.argtypes = [descp, vp, vp, vp, ctypes.POINTER(LaunchOpts), vp]
         lib.zmc_debug_words.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
@@ -143,7 +144,8 @@ def load():
         lib.zmc_integrand_log.argtypes = [vp]
         lib.zmc_integrand_log.restype = ctypes.c_char_p
         lib.zmc_integrand_destroy.argtypes = [vp]
-        for name in ("zmc_integrand_create", "zmc_integrand_destroy", "zmc_validate", "zmc_plan", "zmc_scan", "zmc_scan_device",
+        for name in ("zmc_integrand_create", "zmc_integrand_destroy", "zmc_scan_chunked",
+                     "zmc_validate", "zmc_plan", "zmc_scan", "zmc_scan_device",
                      "zmc_scan_device_ex", "zmc_debug_words", "zmc_debug_values",
                      "zmc_batch_plan", "zmc_batch_create", "zmc_batch_launch",
                      "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch",
@@ -303,6 +305,22 @@ def scan_host(spec):
     dp = ctypes.POINTER(ctypes.c_double)
     _check(load().zmc_scan(d.ref, f.ctypes.data_as(dp), s.ctypes.data_as(dp)))
     return f, s
+
+
+def scan_chunked(spec, chunk_points=0, f=None, sigma=None):
+    """(f, sigma) in host memory through the out-of-core entry point: numpy
+    float64 arrays (allocated when None), or any host buffers with
+    `ctypes`/`data_ptr` (pinned torch tensors take the copies directly)."""
+    d = Desc(spec)
+    G = validate(spec)
+    f = np.empty(G, dtype=np.float64) if f is None else f
+    sigma = np.empty(G, dtype=np.float64) if sigma is None else sigma
+
+    def ptr(a):
+        return ctypes.c_void_p(a.data_ptr() if hasattr(a, "data_ptr") else a.ctypes.data)
+
+    _check(load().zmc_scan_chunked(d.ref, ptr(f), ptr(sigma), int(chunk_points)))
+    return f, sigma
 
 
 def debug_words(seed, g, w0, count, stream=None):

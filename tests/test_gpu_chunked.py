@@ -1,0 +1,102 @@
+"""Out-of-core (chunked) scans into host memory (needs an MI355X): every
+chunk runs the whole grid's decomposition, so the results equal an in-core
+scan of the whole grid bit for bit; plus oracle parity on sampled points."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as zo
+from paper_1910_01965_amd import workloads as wl
+
+import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_01965_amd import zmc
+    zmc.load()
+    return torch
+
+
+def _zmc():
+    from paper_1910_01965_amd import zmc
+    return zmc
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _in_core(spec):
+    import torch
+    f, s = _zmc().scan(spec)
+    torch.cuda.synchronize()
+    return f.cpu().numpy(), s.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("chunk", [10007, 65536, 0])
+def test_chunked_equals_in_core_point_major(precision, chunk):
+    spec = wl.gauss_2p(points_per_axis=300, samples=2051, precision=precision)
+    _say(f"chunked {spec.name} {precision} chunk={chunk}")
+    f, s = _zmc().scan_chunked(spec, chunk)
+    fa, sa = _in_core(spec)
+    assert np.array_equal(f, fa) and np.array_equal(s, sa)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_chunked_equals_in_core_sample_major(precision):
+    spec = wl.plain_fp64(points=1000, samples=1 << 14).with_(precision=precision)
+    f, s = _zmc().scan_chunked(spec, 333)
+    fa, sa = _in_core(spec)
+    assert np.array_equal(f, fa) and np.array_equal(s, sa)
+    f_ref, s_ref = zo.scan(spec)
+    parity.check(f, s, f_ref, s_ref, spec.samples, precision, "chunked sample-major")
+
+
+def test_chunked_pinned_outputs_and_oracle():
+    import torch
+    spec = wl.cosexp_4p(points_per_axis=20, samples=1024, precision="fp32")
+    f = torch.empty(spec.G, dtype=torch.float64, pin_memory=True)
+    s = torch.empty(spec.G, dtype=torch.float64, pin_memory=True)
+    _zmc().scan_chunked(spec, 30000, f, s)
+    fa, sa = _in_core(spec)
+    assert np.array_equal(f.numpy(), fa) and np.array_equal(s.numpy(), sa)
+    idx = np.sort(np.random.default_rng(4).choice(spec.G, 64, replace=False)).astype(np.uint64)
+    f_ref, s_ref = zo.scan(spec, idx)
+    ii = idx.astype(np.int64)
+    parity.check(f.numpy()[ii], s.numpy()[ii], f_ref, s_ref, spec.samples, "fp32", "chunked pinned",
+                 small_n=True, volume=2.0)
+
+
+def test_chunked_user_integrand():
+    src = ("template <typename T> __device__ T integrand(const T* y, const T* x, const T* p) {\n"
+           "  return exp(-x[0] * (y[0] - p[0]) * (y[0] - p[0])) * cos(x[1] * y[1]);\n}\n")
+    spec = wl.ScanSpec("user", [np.linspace(0.5, 4, 70), np.linspace(0, 3, 90)], np.zeros(2),
+                       np.ones(2), 1025, 31, "fp64", source=src, params=np.array([0.25]))
+    f, s = _zmc().scan_chunked(spec, 999)
+    fa, sa = _in_core(spec)
+    assert np.array_equal(f, fa) and np.array_equal(s, sa)
+
+
+def test_chunked_many_chunks():
+    """12 million points in 1M-point chunks: in-core equality and sampled
+    oracle parity, every chunk boundary included."""
+    spec = wl.ScanSpec("sin_sum", [np.linspace(0, 1, 4000), np.linspace(0, 2, 3000)], np.zeros(2),
+                       np.ones(2), 64, 41, "fp32")
+    C = 1 << 20
+    f, s = _zmc().scan_chunked(spec, C)
+    fa, sa = _in_core(spec)
+    assert np.array_equal(f, fa) and np.array_equal(s, sa)
+    edges = np.arange(C, spec.G, C)
+    idx = np.unique(np.concatenate([edges - 1, edges, [0, spec.G - 1]])).astype(np.uint64)
+    f_ref, s_ref = zo.scan(spec, idx)
+    ii = idx.astype(np.int64)
+    parity.check(f[ii], s[ii], f_ref, s_ref, spec.samples, "fp32", "chunk boundaries", small_n=True)
