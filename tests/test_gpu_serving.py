@@ -57,9 +57,11 @@ def _alone(spec):
 
 
 def test_mix_equals_alone_and_oracle():
+    """64 requests through the server, each re-run alone: bitwise equal; every
+    fourth one against the oracle."""
     import torch
     zmc = _zmc()
-    specs = _requests(24)
+    specs = _requests(64)
     srv = zmc.Server(max_slots=8, slice_tiles=512)
     tickets = []
     for i, sp in enumerate(specs):
