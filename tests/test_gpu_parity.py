@@ -150,6 +150,27 @@ def test_gauss_full_grid_sampled(precision):
     assert ok, cmsg
 
 
+def test_gauss_full_grid_every_point():
+    """The 1e6-point Gaussian grid at 2^14 samples, every point of both GPU
+    paths against the oracle.  The oracle runs on up to 16 host threads
+    (its C calls release the interpreter lock; it keeps no shared state)."""
+    import concurrent.futures as cfut
+    import os
+    spec = wl.gauss_2p(precision="fp64")
+    f64, s64 = _run(spec)
+    f32, s32 = _run(spec.with_(precision="fp32"))
+    parts = np.array_split(np.arange(spec.G, dtype=np.uint64), 128)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    _say(f"oracle on all {spec.G} points, {workers} threads")
+    with cfut.ThreadPoolExecutor(workers) as ex:
+        res = list(ex.map(lambda idx: zo.scan(spec, idx), parts))
+    f_ref = np.concatenate([r[0] for r in res])
+    s_ref = np.concatenate([r[1] for r in res])
+    for f, s, prec in ((f64, s64, "fp64"), (f32, s32, "fp32")):
+        _, _, msg = parity.check(f, s, f_ref, s_ref, spec.samples, prec, f"{spec.name} every point")
+        _say(msg)
+
+
 def test_cosexp_full_grid_subsample():
     spec = wl.cosexp_4p(precision="fp32")
     _say(f"scan {spec.name} full grid fp32")
