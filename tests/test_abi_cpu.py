@@ -199,3 +199,23 @@ def test_user_scans_are_not_batched(lib):
 def ctypes_u64():
     import ctypes
     return ctypes.byref(ctypes.c_uint64())
+
+
+def test_chunked_scan_argument_checks(lib):
+    import ctypes
+    d = zmc.Desc(GOOD)
+    f = np.zeros(GOOD.G)
+    s = np.zeros(GOOD.G)
+    vp = ctypes.c_void_p
+    assert lib.zmc_scan_chunked(d.ref, None, vp(s.ctypes.data), 0) == 1
+    assert lib.zmc_scan_chunked(d.ref, vp(f.ctypes.data), None, 0) == 1
+    bad = zmc.Desc(GOOD.with_(samples=1))
+    assert lib.zmc_scan_chunked(bad.ref, vp(f.ctypes.data), vp(s.ctypes.data), 0) == 1
+    no_lists = zmc.Desc(GOOD)
+    no_lists.c.axis_vals = None
+    assert lib.zmc_scan_chunked(no_lists.ref, vp(f.ctypes.data), vp(s.ctypes.data), 0) == 1
+    # a valid request on a host without a GPU fails cleanly (no device)
+    import torch
+    if not torch.cuda.is_available():
+        assert lib.zmc_scan_chunked(d.ref, vp(f.ctypes.data), vp(s.ctypes.data), 7) == 3
+        assert lib.zmc_last_error().decode()
