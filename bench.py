@@ -177,10 +177,19 @@ def cpu_baseline(spec, points, seed=0):
     t0 = time.perf_counter()
     zo.scan(spec.with_(precision="fp64"), idx)
     dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
+    full_s = spec.G * spec.samples / (points * spec.samples / dt)
     return {"value": points * spec.samples / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
             "sample": f"{points} seeded random grid points of {spec.name} (all {spec.samples} samples "
                       f"each, {points * spec.samples:.3g} samples), single-threaded FP64 oracle, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "host": {"cpu": model, "logical_cpus": os.cpu_count()},
+            "full_grid_one_core_s_extrapolated": full_s}
 
 
 def copy_probe(nbytes=1 << 30, reps=3):
