@@ -166,7 +166,8 @@ zmc_status zmc_scan_device(const zmc_scan_desc* desc, const double* d_axis_vals,
  * chunk i-1 is copied back over PCIe and, when f and sigma are pageable,
  * from pinned staging into them on host threads; outputs in pinned memory
  * (hipHostMalloc) take the copies directly.  Device memory: the lists plus
- * 2 x 16 B x chunk_points plus the chunk's split partials.  Synchronous. */
+ * 2 x 16 B x chunk_points plus the chunk's split partials.  Synchronous.
+ * f and sigma must be host memory (ZMC_E_INVALID for device pointers). */
 zmc_status zmc_scan_chunked(const zmc_scan_desc* desc, double* f, double* sigma,
                             uint64_t chunk_points);
 

@@ -427,12 +427,18 @@ zmc_status zmc_scan_chunked(const zmc_scan_desc* desc, double* f, double* sigma,
   const size_t off_ws = off_out + 2 * slot_bytes;
   const size_t total = off_ws + cp.workspace_bytes;
   // outputs already in pinned host memory take the copies directly
-  bool pinned = true;
+  bool pinned = true, on_device = false;
   for (double* ptr : {f, sigma}) {
     hipPointerAttribute_t a;
-    if (hipPointerGetAttributes(&a, ptr) != hipSuccess || a.type != hipMemoryTypeHost) pinned = false;
+    if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+      pinned = false;  // pageable host memory is unknown to HIP
+      continue;
+    }
+    if (a.type == hipMemoryTypeDevice) on_device = true;
+    if (a.type != hipMemoryTypeHost) pinned = false;
   }
   (void)hipGetLastError();  // pageable memory can leave an error behind
+  if (on_device) return fail(ZMC_E_INVALID, "f and sigma must be host memory (device outputs: zmc_scan_device)");
 
   char* dmem = nullptr;
   double* stage = nullptr;

@@ -100,3 +100,14 @@ def test_chunked_many_chunks():
     f_ref, s_ref = zo.scan(spec, idx)
     ii = idx.astype(np.int64)
     parity.check(f[ii], s[ii], f_ref, s_ref, spec.samples, "fp32", "chunk boundaries", small_n=True)
+
+
+def test_chunked_rejects_device_outputs():
+    import torch
+    zmc = _zmc()
+    spec = wl.gauss_2p(points_per_axis=20, samples=64, precision="fp32")
+    f = torch.empty(spec.G, dtype=torch.float64, device="cuda")
+    s = torch.empty(spec.G, dtype=torch.float64, device="cuda")
+    with pytest.raises(zmc.ZmcError) as ei:
+        zmc.scan_chunked(spec, 0, f, s)
+    assert ei.value.status == 1
