@@ -127,3 +127,37 @@ def test_user_reproduces_compiled_cosexp():
     fa, sa, fu, su = (t.cpu().numpy() for t in (fa, sa, fu, su))
     scale = np.maximum(np.abs(fa), sa * np.sqrt(base.samples))
     assert np.max(np.abs(fu - fa) / scale) < 1e-12 and np.max(np.abs(su - sa) / sa) < 1e-10
+
+
+def test_user_integrand_shared_by_threads():
+    """Threads sharing one handle compile and load its variants concurrently;
+    every result equals the same scan run alone afterwards."""
+    import threading
+
+    import torch
+    zmc = _zmc()
+    src = HEAD + "  T s = p[0];\n  for (int k = 0; k < 2; ++k) s += x[0] * y[k];\n  return sin(s) + T(2);\n}\n"
+    specs = [wl.ScanSpec("user", [np.linspace(0, 1, 37)], np.zeros(N), np.ones(N), 999, 50 + N, prec,
+                         source=src, params=np.array([0.1]))
+             for N in (2, 3, 4) for prec in ("fp64", "fp32")]
+    out = [None] * len(specs)
+    errors = []
+
+    def run(i):
+        try:
+            f, s = zmc.scan(specs[i])
+            torch.cuda.synchronize()
+            out[i] = (f.cpu().numpy(), s.cpu().numpy())
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    th = [threading.Thread(target=run, args=(i,)) for i in range(len(specs))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    for sp, (f, s) in zip(specs, out):
+        fa, sa = zmc.scan(sp)
+        torch.cuda.synchronize()
+        assert np.array_equal(f, fa.cpu().numpy()) and np.array_equal(s, sa.cpu().numpy())
