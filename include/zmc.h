@@ -207,7 +207,8 @@ zmc_status zmc_debug_values(const zmc_scan_desc* desc, const double* d_axis_vals
  * report errors (ZMC_E_INVALID with the compiler's log in zmc_last_error);
  * every (precision, N, M) variant a scan needs is then compiled on first use
  * (a few seconds) and kept, and loaded once per device.  It needs no GPU.
- * The handle may be shared by threads; destroy it after its scans finished.
+ * The handle may be shared by threads.  zmc_integrand_destroy waits for
+ * each device it was loaded on to go idle before unloading its kernels.
  * ZMC_USER scans run through zmc_scan, zmc_scan_device(_ex), zmc_plan,
  * zmc_validate and zmc_debug_values; batches and the server return
  * ZMC_E_UNSUPPORTED for them. */

@@ -7,6 +7,7 @@ fails loudly when libzmc.so has not been built: there is no fallback.
 """
 import ctypes
 import os
+import threading
 
 import numpy as np
 
@@ -191,15 +192,18 @@ class Integrand:
 
 
 _integrands = {}
+_integrands_lock = threading.Lock()
 
 
 def integrand(source):
-    """The process-wide Integrand for `source` (compiled once)."""
+    """The process-wide Integrand for `source` (compiled once, kept for the
+    life of the process, so its kernels are never unloaded under a scan)."""
     if not source:
         raise ZmcError(1, "family 'user' needs ScanSpec.source")
-    it = _integrands.get(source)
-    if it is None:
-        it = _integrands[source] = Integrand(source)
+    with _integrands_lock:
+        it = _integrands.get(source)
+        if it is None:
+            it = _integrands[source] = Integrand(source)
     return it
 
 
