@@ -209,9 +209,10 @@ zmc_status zmc_debug_values(const zmc_scan_desc* desc, const double* d_axis_vals
  * (a few seconds) and kept, and loaded once per device.  It needs no GPU.
  * The handle may be shared by threads.  zmc_integrand_destroy waits for
  * each device it was loaded on to go idle before unloading its kernels.
- * ZMC_USER scans run through zmc_scan, zmc_scan_device(_ex), zmc_plan,
- * zmc_validate and zmc_debug_values; batches and the server return
- * ZMC_E_UNSUPPORTED for them. */
+ * ZMC_USER scans run through every entry point: single scans, chunked
+ * scans, batches (one persistent kernel per (handle, precision, N, M), built
+ * at batch creation) and the server (built when a request is admitted).  The
+ * handle must outlive every batch and request that uses it. */
 zmc_status zmc_integrand_create(const char* source, zmc_integrand** out);
 
 /* Compiler log of the handle's last build (empty when it produced none). */

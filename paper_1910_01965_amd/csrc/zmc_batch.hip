@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <new>
 #include <vector>
 
@@ -66,15 +67,23 @@ constexpr size_t kAlign = 256;
 uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// One persistent kernel per key: (precision, family, N) for the compiled-in
+// families (family -1: the any-family kernel), plus the handle and M for a
+// user integrand, whose kernel is built at run time for that shape.
 struct VariantKey {
   int precision, family, N;
+  const zmc_integrand* integrand = nullptr;
+  int M = 0;
   bool operator<(const VariantKey& o) const {
     if (precision != o.precision) return precision < o.precision;
     if (family != o.family) return family < o.family;
-    return N < o.N;
+    if (N != o.N) return N < o.N;
+    if (integrand != o.integrand) return std::less<const zmc_integrand*>()(integrand, o.integrand);
+    return M < o.M;
   }
   bool operator==(const VariantKey& o) const {
-    return precision == o.precision && family == o.family && N == o.N;
+    return precision == o.precision && family == o.family && N == o.N &&
+           integrand == o.integrand && M == o.M;
   }
 };
 
@@ -91,6 +100,7 @@ struct Variant {
   VariantKey key;
   uint32_t begin = 0, end = 0;
   unsigned blocks = 0;
+  zmc::UserKernels user;  // family ZMC_USER: the run-time-built kernels
 };
 
 struct TileCost {
@@ -130,15 +140,16 @@ zmc_status plan_batch(const zmc_scan_desc* scans, int32_t n, const zmc_batch_opt
       snprintf(why, sizeof(why), "%s", zmc_last_error());
       return fail(st, "scan %d: %s", i, why);
     }
-    if (scans[i].family == ZMC_USER)
-      return fail(ZMC_E_UNSUPPORTED, "scan %d: user integrands run through the single-scan entry points", i);
     ScanPlanB& sp = bp->scans[(size_t)i];
     st = plan_scan(&scans[i], G, o, &sp);
     if (st != ZMC_OK) return st;
     for (int l = 0; l < scans[i].M; ++l) sp.axis_len_total += (uint64_t)scans[i].axis_len[l];
     total_tiles += sp.tiles;
     if (total_tiles > kMaxTiles) return fail(ZMC_E_UNSUPPORTED, "batch has more than 2^31 tiles");
-    if (o && o->one_kernel)
+    if (scans[i].family == ZMC_USER)
+      keys.push_back(VariantKey{scans[i].precision, ZMC_USER, scans[i].N, scans[i].integrand,
+                                scans[i].M});
+    else if (o && o->one_kernel)
       keys.push_back(VariantKey{scans[i].precision, -1, 0});
     else
       keys.push_back(VariantKey{scans[i].precision, scans[i].family, scans[i].N});
@@ -255,6 +266,9 @@ hipError_t enqueue(zmc_batch* b, hipStream_t s, const std::vector<hipStream_t>& 
     if (e == hipSuccess && var.key.family < 0)
       e = zmc::launch_batch_any(var.key.precision, b->d_scans, b->d_tiles, var.begin, var.end,
                                 b->d_counters + v, var.blocks, sv);
+    else if (e == hipSuccess && var.key.family == ZMC_USER)
+      e = zmc::launch_user_batch(var.user, b->d_scans, b->d_tiles, var.begin, var.end,
+                                 b->d_counters + v, var.blocks, sv);
     else if (e == hipSuccess)
       e = zmc::launch_batch_variant(var.key.precision, var.key.family, var.key.N, b->d_scans,
                                     b->d_tiles, var.begin, var.end, b->d_counters + v, var.blocks,
@@ -307,6 +321,11 @@ zmc_status zmc_batch_create(const zmc_scan_desc* scans, int32_t n_scans,
   BatchPlan bp;
   zmc_status st = plan_batch(scans, n_scans, &o, true, &bp);
   if (st != ZMC_OK) return st;
+  for (Variant& var : bp.variants) {
+    if (var.key.family != ZMC_USER) continue;
+    st = zmc::user_kernels(var.key.integrand, var.key.precision, var.key.N, var.key.M, &var.user);
+    if (st != ZMC_OK) return st;
+  }
   for (int i = 0; i < n_scans; ++i) {
     if (d_f[i] == nullptr || d_sigma[i] == nullptr)
       return fail(ZMC_E_INVALID, "scan %d: output pointer is NULL", i);
@@ -385,9 +404,10 @@ zmc_status zmc_batch_create(const zmc_scan_desc* scans, int32_t n_scans,
   for (size_t v = 0; e == hipSuccess && v < b->variants.size(); ++v) {
     Variant& var = b->variants[v];
     int per_cu = 0;
-    e = var.key.family < 0
-            ? zmc::batch_any_occupancy(var.key.precision, &per_cu)
-            : zmc::batch_occupancy(var.key.precision, var.key.family, var.key.N, &per_cu);
+    e = var.key.family < 0          ? zmc::batch_any_occupancy(var.key.precision, &per_cu)
+        : var.key.family == ZMC_USER ? zmc::user_batch_occupancy(var.user, &per_cu)
+                                     : zmc::batch_occupancy(var.key.precision, var.key.family,
+                                                            var.key.N, &per_cu);
     if (per_cu < 1) per_cu = 1;
     const uint64_t want = (uint64_t)cu * (uint64_t)per_cu;
     const uint64_t tiles = var.end - var.begin;

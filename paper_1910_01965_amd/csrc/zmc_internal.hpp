@@ -65,13 +65,17 @@ hipError_t launch_merge_splits(const ScanParams& p, hipStream_t stream);
 
 // Kernels of a user integrand for one (precision, N, M), built on first use.
 struct UserKernels {
-  hipFunction_t pm = nullptr, sm = nullptr, values = nullptr;
+  hipFunction_t pm = nullptr, sm = nullptr, values = nullptr, batch = nullptr;
 };
 zmc_status user_kernels(const zmc_integrand* h, int precision, int N, int M, UserKernels* out);
 hipError_t launch_user_scan(const UserKernels& k, const ScanParams& p, const Plan& plan,
                             hipStream_t stream, hipEvent_t ev_begin, hipEvent_t ev_end);
 hipError_t launch_user_values(const UserKernels& k, const ScanParams& p, uint64_t g, uint64_t s0,
                               int64_t count, double* out, hipStream_t stream);
+hipError_t user_batch_occupancy(const UserKernels& k, int* blocks_per_cu);
+hipError_t launch_user_batch(const UserKernels& k, const ScanParams* scans, const Tile* tiles,
+                             uint32_t begin, uint32_t end, uint32_t* counter, unsigned blocks,
+                             hipStream_t stream);
 hipError_t launch_debug_values(const ScanParams& p, int precision, uint64_t g, uint64_t s0,
                                int64_t count, double* out, hipStream_t stream);
 

@@ -167,6 +167,32 @@ __device__ __forceinline__ void sample_major_body(const ScanParams& p, double* l
   for (uint64_t g = blockIdx.x; g < p.G; g += gridDim.x) sm_tile<Fam, T, N>(p, g, blockIdx.y, lds);
 }
 
+// Persistent batch body: the block pops tiles [begin, end) of the tile table
+// through one atomic counter and runs them until the table is exhausted;
+// every block reaches that exit.  `next` and `lds` are the kernel's shared
+// memory (one word, 3 x 16 doubles).
+template <class Fam, typename T, int N>
+__device__ __forceinline__ void batch_body(const ScanParams* __restrict__ scans,
+                                           const Tile* __restrict__ tiles, uint32_t begin,
+                                           uint32_t end, uint32_t* counter, uint32_t* next,
+                                           double* lds) {
+  for (;;) {
+    __syncthreads();  // the previous tile is done with `next` and `lds`
+    if (threadIdx.x == 0) *next = begin + atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t t = *next;
+    if (t >= end) break;
+    const Tile tl = tiles[t];
+    const ScanParams& p = scans[tl.scan];
+    const uint64_t sp = tl.split_mode & ~kTileSampleMajor;
+    if (tl.split_mode & kTileSampleMajor) {
+      sm_tile<Fam, T, N>(p, tl.first, sp, lds);
+    } else {
+      pm_tile<Fam, T, N>(p, tl.first, sp);
+    }
+  }
+}
+
 template <class Fam, typename T, int N>
 __device__ __forceinline__ void debug_values_body(const ScanParams& p, uint64_t g, uint64_t s0,
                                                   int64_t count, double* out) {

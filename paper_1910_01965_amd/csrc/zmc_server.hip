@@ -37,7 +37,7 @@ struct Request {
   uint64_t ticket = 0;
   zmc_scan_desc desc{};
   std::vector<int64_t> axis_len;
-  std::vector<double> axis_vals, lo, hi;
+  std::vector<double> axis_vals, lo, hi, params;
   const double* d_axis_user = nullptr;
   double* d_f = nullptr;
   double* d_sigma = nullptr;
@@ -47,6 +47,8 @@ struct Request {
   uint64_t tile_samples = 1;  // samples per tile, averaged over the request's tiles
   uint64_t staged_doubles = 0;
   uint64_t footprint = 0;
+  zmc::UserKernels user;      // family ZMC_USER: kernels built for this shape
+  unsigned user_blocks = 0;   // resident blocks of the user batch kernel
   void* dmem = nullptr;
   int alloc_stream = 0;
   int slot = -1;
@@ -72,6 +74,8 @@ struct zmc_server {
   int device = 0;
   hipStream_t streams[kStreams] = {nullptr, nullptr};
   unsigned blocks32 = 1, blocks64 = 1;
+  int cu = 1;
+  int counters_per_slot = 2;  // FP32 and FP64 any-family kernels, then user variants
   int ring = 3;
   // device memory: slot table | tile ring | counter ring | merge ring
   void* dmem = nullptr;
@@ -191,15 +195,39 @@ hipError_t launch_slice(zmc_server* s, int si, Slice* out) {
     used += more;
     used_samples += more * r.tile_samples;
   }
+  // tile table: compiled-in FP32 tiles, FP64 tiles, then one group per user
+  // variant (integrand, precision, N, M)
   uint32_t n32 = 0, n = 0;
   for (int pass = 0; pass < 2; ++pass) {
     const int prec = pass == 0 ? ZMC_FP32_MERGE64 : ZMC_FP64;
     for (auto& tk : take) {
       Request& r = *tk.first;
-      if (r.desc.precision != prec) continue;
+      if (r.desc.precision != prec || r.desc.family == ZMC_USER) continue;
       for (uint64_t t = 0; t < tk.second; ++t) ht[n++] = tile_of(r, r.next_tile + t);
     }
     if (pass == 0) n32 = n;
+  }
+  const uint32_t n_builtin = n;
+  struct UserGroup {
+    const Request* first;
+    uint32_t begin, end;
+  };
+  std::vector<UserGroup> groups;
+  std::vector<bool> placed(take.size(), false);
+  for (size_t a = 0; a < take.size(); ++a) {
+    const Request& ra = *take[a].first;
+    if (ra.desc.family != ZMC_USER || placed[a]) continue;
+    UserGroup grp{&ra, n, n};
+    for (size_t b = a; b < take.size(); ++b) {
+      Request& rb = *take[b].first;
+      if (placed[b] || rb.desc.family != ZMC_USER || rb.desc.integrand != ra.desc.integrand ||
+          rb.desc.precision != ra.desc.precision || rb.desc.N != ra.desc.N || rb.desc.M != ra.desc.M)
+        continue;
+      placed[b] = true;
+      for (uint64_t t = 0; t < take[b].second; ++t) ht[n++] = tile_of(rb, rb.next_tile + t);
+    }
+    grp.end = n;
+    groups.push_back(grp);
   }
   std::vector<uint32_t> merges;
   uint64_t max_g = 0;
@@ -214,15 +242,21 @@ hipError_t launch_slice(zmc_server* s, int si, Slice* out) {
   }
   hipStream_t st = s->streams[si];
   zmc::Tile* dt = s->d_tiles + (size_t)ring_slot * cap;
-  uint32_t* dc = s->d_counters + 2 * ring_slot;
+  uint32_t* dc = s->d_counters + (size_t)s->counters_per_slot * ring_slot;
   // the other stream's admissions (slot table, staged lists) come first
   hipError_t e = hipStreamWaitEvent(st, s->admit_events[1 - si], 0);
   if (e == hipSuccess) e = hipMemcpyAsync(dt, ht, sizeof(zmc::Tile) * n, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = zmc::launch_reset_counters(dc, 2, st);
+  if (e == hipSuccess) e = zmc::launch_reset_counters(dc, 2 + (int)groups.size(), st);
   if (e == hipSuccess && n32 > 0)
     e = zmc::launch_batch_any(ZMC_FP32_MERGE64, s->d_slots, dt, 0, n32, dc, s->blocks32, st);
-  if (e == hipSuccess && n > n32)
-    e = zmc::launch_batch_any(ZMC_FP64, s->d_slots, dt, n32, n, dc + 1, s->blocks64, st);
+  if (e == hipSuccess && n_builtin > n32)
+    e = zmc::launch_batch_any(ZMC_FP64, s->d_slots, dt, n32, n_builtin, dc + 1, s->blocks64, st);
+  for (size_t gi = 0; e == hipSuccess && gi < groups.size(); ++gi) {
+    const UserGroup& grp = groups[gi];
+    const unsigned blocks = std::max(1u, std::min(grp.first->user_blocks, grp.end - grp.begin));
+    e = zmc::launch_user_batch(grp.first->user, s->d_slots, dt, grp.begin, grp.end, dc + 2 + gi,
+                               blocks, st);
+  }
   if (e == hipSuccess && !merges.empty()) {
     // a finishing request's earlier tiles may sit in the other stream's slice
     if (s->slice_count > 0) e = hipStreamWaitEvent(st, s->done_events[(ring_slot + s->ring - 1) % s->ring], 0);
@@ -310,6 +344,17 @@ void run(zmc_server* s) {
       }
       if (s->bytes_in_use + r->footprint > s->opts.hbm_budget_bytes) break;
       s->pending.pop_front();
+      if (r->desc.family == ZMC_USER) {
+        // built (first use of this shape) and loaded on the server's device
+        const zmc_status us = zmc::user_kernels(r->desc.integrand, r->desc.precision, r->desc.N,
+                                                r->desc.M, &r->user);
+        int per_cu = 0;
+        if (us != ZMC_OK || zmc::user_batch_occupancy(r->user, &per_cu) != hipSuccess) {
+          finish(s, r, us != ZMC_OK ? us : ZMC_E_DEVICE);
+          continue;
+        }
+        r->user_blocks = (unsigned)std::max(1, s->cu * std::max(1, per_cu));
+      }
       if (admit(s, r, si) != hipSuccess) {
         finish(s, r, ZMC_E_DEVICE);
         broken = true;
@@ -405,6 +450,7 @@ zmc_status zmc_server_create(const zmc_server_opts* opts, zmc_server** out) {
   int per32 = 1, per64 = 1;
   if (e == hipSuccess) e = zmc::batch_any_occupancy(ZMC_FP32_MERGE64, &per32);
   if (e == hipSuccess) e = zmc::batch_any_occupancy(ZMC_FP64, &per64);
+  s->cu = std::max(1, cu);
   s->blocks32 = (unsigned)std::max(1, cu * std::max(1, per32));
   s->blocks64 = (unsigned)std::max(1, cu * std::max(1, per64));
   if (o.slice_tiles <= 0) o.slice_tiles = (int32_t)std::min<uint64_t>(64ull * s->blocks32, 1u << 20);
@@ -412,7 +458,9 @@ zmc_status zmc_server_create(const zmc_server_opts* opts, zmc_server** out) {
   const size_t cap = (size_t)o.slice_tiles, ring = (size_t)s->ring, slots = (size_t)o.max_slots;
   const size_t off_tiles = align_up(sizeof(zmc::ScanParams) * slots);
   const size_t off_counters = off_tiles + align_up(sizeof(zmc::Tile) * cap * ring);
-  const size_t off_merge = off_counters + align_up(sizeof(uint32_t) * 2 * ring);
+  s->counters_per_slot = 2 + o.max_slots;
+  const size_t off_merge =
+      off_counters + align_up(sizeof(uint32_t) * (size_t)s->counters_per_slot * ring);
   const size_t total = off_merge + align_up(sizeof(uint32_t) * slots * ring);
   if (e == hipSuccess) e = hipMalloc(&s->dmem, total);
   if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_slots, sizeof(zmc::ScanParams) * slots, 0);
@@ -454,8 +502,6 @@ zmc_status zmc_server_submit(zmc_server* s, const zmc_scan_desc* desc, const dou
   uint64_t G = 0;
   zmc_status st = zmc::validate_desc(desc, &G);
   if (st != ZMC_OK) return st;
-  if (desc->family == ZMC_USER)
-    return fail(ZMC_E_UNSUPPORTED, "user integrands run through the single-scan entry points");
   if (d_f == nullptr || d_sigma == nullptr) return fail(ZMC_E_INVALID, "d_f or d_sigma is NULL");
   if (desc->M > 0 && d_axis_vals == nullptr && desc->axis_vals == nullptr)
     return fail(ZMC_E_INVALID, "no parameter lists (host or device)");
@@ -474,7 +520,8 @@ zmc_status zmc_server_submit(zmc_server* s, const zmc_scan_desc* desc, const dou
   r->desc.axis_vals = r->axis_vals.empty() ? nullptr : r->axis_vals.data();
   r->desc.lo = r->lo.data();
   r->desc.hi = r->hi.data();
-  r->desc.params = nullptr;
+  r->params.assign(desc->params, desc->params + std::max(0, desc->n_params));
+  r->desc.params = r->params.empty() ? nullptr : r->params.data();
   r->d_axis_user = d_axis_vals;
   r->d_f = d_f;
   r->d_sigma = d_sigma;

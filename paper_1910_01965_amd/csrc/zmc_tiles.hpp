@@ -30,21 +30,7 @@ __global__ __launch_bounds__(256) void k_batch(const ScanParams* __restrict__ sc
                                                uint32_t end, uint32_t* counter) {
   __shared__ uint32_t next;
   __shared__ double lds[48];
-  for (;;) {
-    __syncthreads();  // the previous tile is done with `next` and `lds`
-    if (threadIdx.x == 0) next = begin + atomicAdd(counter, 1u);
-    __syncthreads();
-    const uint32_t t = next;
-    if (t >= end) break;
-    const Tile tl = tiles[t];
-    const ScanParams& p = scans[tl.scan];
-    const uint64_t sp = tl.split_mode & ~kTileSampleMajor;
-    if (tl.split_mode & kTileSampleMajor) {
-      sm_tile<Fam, T, N>(p, tl.first, sp, lds);
-    } else {
-      pm_tile<Fam, T, N>(p, tl.first, sp);
-    }
-  }
+  batch_body<Fam, T, N>(scans, tiles, begin, end, counter, &next, lds);
 }
 
 // One tile of any family and dimension in working precision T: the switch

@@ -188,12 +188,15 @@ def test_user_descriptor_validation(lib):
         zmc.validate(GOOD.with_(params=np.ones(1)))
 
 
-def test_user_scans_are_not_batched(lib):
+def test_user_scans_plan_as_their_own_variants(lib):
     spec = wl.ScanSpec("user", [np.linspace(0, 1, 5)], np.zeros(2), np.ones(2), 100, 3,
                        source=USER_SRC, params=np.array([0.5, 2.0]))
-    with pytest.raises(zmc.ZmcError) as ei:
-        zmc.batch_plan([GOOD, spec], cu_count=256)
-    assert ei.value.status == 4 and "scan 1" in str(ei.value)
+    info = zmc.batch_plan([GOOD, spec, spec.with_(seed=4)], cu_count=256)
+    assert info["scans"] == 3 and info["variants"] == 2
+    # another shape of the same integrand is another kernel; one_kernel keeps it apart
+    info = zmc.batch_plan([GOOD, spec, spec.with_(axes=[np.arange(3.0)] * 2)], cu_count=256,
+                          one_kernel=1)
+    assert info["variants"] == 3
 
 
 def ctypes_u64():
