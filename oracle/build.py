@@ -21,5 +21,19 @@ def build(out=LIB, src=SRC, cc="gcc", extra=()):
     return out
 
 
+CLI_SRC = os.path.join(HERE, "zmc_oracle_cli.c")
+CLI = os.path.join(HERE, "zmc_oracle_cli")
+
+
+def build_cli(out=CLI, cc="gcc"):
+    """Compile the command-line front end (oracle + CLI) into `out`."""
+    cmd = [cc, "-std=c99", "-O2", "-Wall", "-Wextra", "-I", HERE, CLI_SRC, SRC, "-o", out + ".tmp",
+           "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
 if __name__ == "__main__":
     print(build())
+    print(build_cli())
