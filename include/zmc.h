@@ -171,6 +171,16 @@ zmc_status zmc_scan_device(const zmc_scan_desc* desc, const double* d_axis_vals,
 zmc_status zmc_scan_chunked(const zmc_scan_desc* desc, double* f, double* sigma,
                             uint64_t chunk_points);
 
+/* Points [g_begin, g_end) of the grid (flat C-order indices), computed as
+ * zmc_scan_chunked computes the whole grid, into host arrays of
+ * g_end - g_begin doubles (f[i] is point g_begin + i).  The values equal
+ * that slice of a scan of the whole grid bit for bit, so ranges can run in
+ * separate processes or on separate devices and be concatenated, and an
+ * interrupted scan resumes from its first unfinished range.  ZMC_E_INVALID
+ * for an empty range or one outside the grid. */
+zmc_status zmc_scan_range(const zmc_scan_desc* desc, uint64_t g_begin, uint64_t g_end,
+                          double* f, double* sigma, uint64_t chunk_points);
+
 /* zmc_scan_device with an explicit decomposition (opts may be NULL). */
 zmc_status zmc_scan_device_ex(const zmc_scan_desc* desc, const double* d_axis_vals,
                               double* d_f, double* d_sigma,

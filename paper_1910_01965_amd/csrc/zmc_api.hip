@@ -400,8 +400,20 @@ zmc_status zmc_scan_chunked(const zmc_scan_desc* desc, double* f, double* sigma,
   uint64_t G = 0;
   zmc_status st = validate(desc, &G);
   if (st != ZMC_OK) return st;
+  return zmc_scan_range(desc, 0, G, f, sigma, chunk_points);
+}
+
+zmc_status zmc_scan_range(const zmc_scan_desc* desc, uint64_t g_begin, uint64_t g_end, double* f,
+                          double* sigma, uint64_t chunk_points) {
+  uint64_t G = 0;
+  zmc_status st = validate(desc, &G);
+  if (st != ZMC_OK) return st;
   if (desc->M > 0 && desc->axis_vals == nullptr) return fail(ZMC_E_INVALID, "axis_vals is NULL with M > 0");
   if (f == nullptr || sigma == nullptr) return fail(ZMC_E_INVALID, "f or sigma is NULL");
+  if (g_begin >= g_end || g_end > G)
+    return fail(ZMC_E_INVALID, "range [%llu, %llu) is empty or outside the grid of %llu points",
+                (unsigned long long)g_begin, (unsigned long long)g_end, (unsigned long long)G);
+  const uint64_t R = g_end - g_begin;  // points of the range; f[i] is point g_begin + i
   zmc::UserKernels uk;
   if (desc->family == ZMC_USER) {
     st = zmc::user_kernels(desc->integrand, desc->precision, desc->N, desc->M, &uk);
@@ -413,7 +425,7 @@ zmc_status zmc_scan_chunked(const zmc_scan_desc* desc, double* f, double* sigma,
   st = make_plan(desc, G, nullptr, &full);
   if (st != ZMC_OK) return st;
   const zmc_launch_opts fixed{full.mode, full.block, full.splits, 0, nullptr, nullptr};
-  const uint64_t C = std::min<uint64_t>(G, chunk_points > 0 ? chunk_points : kDefaultChunk);
+  const uint64_t C = std::min<uint64_t>(R, chunk_points > 0 ? chunk_points : kDefaultChunk);
   zmc::Plan cp;
   st = make_plan(desc, C, &fixed, &cp);
   if (st != ZMC_OK) return st;
@@ -467,18 +479,18 @@ zmc_status zmc_scan_chunked(const zmc_scan_desc* desc, double* f, double* sigma,
     }
     for (auto& x : th) x.join();
   };
-  const uint64_t chunks = (G + C - 1) / C;
+  const uint64_t chunks = (R + C - 1) / C;
   uint64_t prev_g0 = 0, prev_n = 0;
   for (uint64_t i = 0; e == hipSuccess && i < chunks; ++i) {
     const int slot = (int)(i & 1);
-    const uint64_t g0 = i * C, n = std::min<uint64_t>(C, G - g0);
+    const uint64_t g0 = i * C, n = std::min<uint64_t>(C, R - g0);  // g0: offset in the range
     double* d_f = (double*)(dmem + off_out + (size_t)slot * slot_bytes);
     double* d_s = d_f + C;
     zmc::Plan pl;
     st = make_plan(desc, n, &fixed, &pl);
     if (st != ZMC_OK) break;
     zmc::ScanParams p;
-    fill_params(desc, n, pl, d_axis, d_f, d_s, &p, g0);
+    fill_params(desc, n, pl, d_axis, d_f, d_s, &p, g_begin + g0);
     if (pl.workspace_bytes > 0) {
       p.part_mean = (double*)(dmem + off_ws);
       p.part_m2 = p.part_mean + (uint64_t)pl.splits * n;

@@ -27,7 +27,7 @@ EXPORTS = ("zmc_last_error", "zmc_version", "zmc_validate", "zmc_plan", "zmc_sca
            "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch", "zmc_tune_source",
            "zmc_server_create", "zmc_server_submit", "zmc_server_poll", "zmc_server_wait",
            "zmc_server_get_stats", "zmc_server_destroy", "zmc_integrand_create",
-           "zmc_integrand_log", "zmc_integrand_destroy", "zmc_scan_chunked")
+           "zmc_integrand_log", "zmc_integrand_destroy", "zmc_scan_chunked", "zmc_scan_range")
 
 
 class ZmcError(RuntimeError):
@@ -114,6 +114,7 @@ def load():
         lib.zmc_plan.argtypes = [descp, ctypes.POINTER(LaunchOpts), ctypes.POINTER(PlanInfo)]
         lib.zmc_scan.argtypes = [descp, dp, dp]
         lib.zmc_scan_chunked.argtypes = [descp, vp, vp, ctypes.c_uint64]
+        lib.zmc_scan_range.argtypes = [descp, ctypes.c_uint64, ctypes.c_uint64, vp, vp, ctypes.c_uint64]
         lib.zmc_scan_device.argtypes = [descp, vp, vp, vp, vp]
         lib.zmc_scan_device_ex.argtypes = [descp, vp, vp, vp, ctypes.POINTER(LaunchOpts), vp]
         lib.zmc_debug_words.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
@@ -146,6 +147,7 @@ def load():
         lib.zmc_integrand_log.restype = ctypes.c_char_p
         lib.zmc_integrand_destroy.argtypes = [vp]
         for name in ("zmc_integrand_create", "zmc_integrand_destroy", "zmc_scan_chunked",
+                     "zmc_scan_range",
                      "zmc_validate", "zmc_plan", "zmc_scan", "zmc_scan_device",
                      "zmc_scan_device_ex", "zmc_debug_words", "zmc_debug_values",
                      "zmc_batch_plan", "zmc_batch_create", "zmc_batch_launch",
@@ -324,6 +326,22 @@ def scan_chunked(spec, chunk_points=0, f=None, sigma=None):
         return ctypes.c_void_p(a.data_ptr() if hasattr(a, "data_ptr") else a.ctypes.data)
 
     _check(load().zmc_scan_chunked(d.ref, ptr(f), ptr(sigma), int(chunk_points)))
+    return f, sigma
+
+
+def scan_range(spec, g_begin, g_end, chunk_points=0, f=None, sigma=None):
+    """(f, sigma) in host memory for grid points [g_begin, g_end): bitwise the
+    same slice of a whole-grid scan (resumable, shardable)."""
+    d = Desc(spec)
+    n = int(g_end) - int(g_begin)
+    f = np.empty(max(n, 0), dtype=np.float64) if f is None else f
+    sigma = np.empty(max(n, 0), dtype=np.float64) if sigma is None else sigma
+
+    def ptr(a):
+        return ctypes.c_void_p(a.data_ptr() if hasattr(a, "data_ptr") else a.ctypes.data)
+
+    _check(load().zmc_scan_range(d.ref, int(g_begin), int(g_end), ptr(f), ptr(sigma),
+                                 int(chunk_points)))
     return f, sigma
 
 

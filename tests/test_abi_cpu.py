@@ -222,3 +222,13 @@ def test_chunked_scan_argument_checks(lib):
     if not torch.cuda.is_available():
         assert lib.zmc_scan_chunked(d.ref, vp(f.ctypes.data), vp(s.ctypes.data), 7) == 3
         assert lib.zmc_last_error().decode()
+
+
+def test_range_scan_argument_checks(lib):
+    import ctypes
+    d = zmc.Desc(GOOD)
+    f = np.zeros(GOOD.G)
+    vp = ctypes.c_void_p
+    assert lib.zmc_scan_range(d.ref, 3, 3, vp(f.ctypes.data), vp(f.ctypes.data), 0) == 1
+    assert lib.zmc_scan_range(d.ref, 0, GOOD.G + 1, vp(f.ctypes.data), vp(f.ctypes.data), 0) == 1
+    assert lib.zmc_scan_range(d.ref, 4, 2, vp(f.ctypes.data), vp(f.ctypes.data), 0) == 1

@@ -111,3 +111,23 @@ def test_chunked_rejects_device_outputs():
     with pytest.raises(zmc.ZmcError) as ei:
         zmc.scan_chunked(spec, 0, f, s)
     assert ei.value.status == 1
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_ranges_concatenate_to_the_whole_scan(precision):
+    """Three ranges with boundaries inside point blocks, computed separately
+    (as separate processes or devices would), and a resumed scan: all equal
+    the whole-grid scan bit for bit."""
+    zmc = _zmc()
+    spec = wl.gauss_2p(points_per_axis=211, samples=1025, precision=precision)
+    fa, sa = _in_core(spec)
+    a, b = 10001, 30013
+    parts = [zmc.scan_range(spec, lo, hi, chunk) for lo, hi, chunk in
+             ((0, a, 4096), (a, b, 0), (b, spec.G, 7777))]
+    f = np.concatenate([p[0] for p in parts])
+    s = np.concatenate([p[1] for p in parts])
+    assert np.array_equal(f, fa) and np.array_equal(s, sa)
+    with pytest.raises(zmc.ZmcError):
+        zmc.scan_range(spec, 5, 5)
+    with pytest.raises(zmc.ZmcError):
+        zmc.scan_range(spec, 0, spec.G + 1)
