@@ -136,3 +136,19 @@ def test_concurrent_submitters():
         fa, sa = _alone(sp)
         assert np.array_equal(f.cpu().numpy(), fa) and np.array_equal(s.cpu().numpy(), sa)
     srv.close()
+
+
+def test_shutdown_drains_pending_requests():
+    """Closing the server with requests still queued (2 slots, 16 requests)
+    returns once all of them have run; their results equal their alone runs."""
+    import torch
+    zmc = _zmc()
+    specs = _requests(16, seed=10, max_samples=1 << 13)
+    srv = zmc.Server(max_slots=2)
+    tickets = [srv.submit(sp) for sp in specs]
+    srv.close()
+    torch.cuda.synchronize()
+    for sp, t in list(zip(specs, tickets))[::3]:
+        f, s = srv.outputs(t)
+        fa, sa = _alone(sp)
+        assert np.array_equal(f.cpu().numpy(), fa) and np.array_equal(s.cpu().numpy(), sa)
