@@ -296,3 +296,26 @@ def test_host_entry_point_matches_device():
     fd, sd = _run(spec)
     fh, sh = _zmc().scan_host(spec)
     assert np.array_equal(fd, fh) and np.array_equal(sd, sh)
+
+
+def test_in_core_scan_past_two_to_the_32():
+    """An in-core scan of 2^32 + 2^16 points (69 GB of outputs): local and
+    global indices past 2^32 on the general counter path.  Sampled points at
+    the start, around 2^32 and at the end meet the oracle bar."""
+    import torch
+    zmc = _zmc()
+    a1, a2 = np.linspace(0.1, 10, (1 << 16) + 1), np.linspace(0.1, 10, 1 << 16)
+    spec = wl.ScanSpec("gauss", [a1, a2], np.zeros(3), np.ones(3), 5, 23, "fp32")
+    T = 1 << 32
+    assert spec.G == T + (1 << 16)
+    assert zmc.plan(spec)["mode"] == "point_major"
+    _say(f"in-core scan of {spec.G} points")
+    f, s = zmc.scan(spec)
+    torch.cuda.synchronize()
+    idx = np.concatenate([np.arange(0, 100), np.arange(T - 100, T + 100), np.arange(spec.G - 100, spec.G)])
+    ii = torch.from_numpy(idx).cuda()
+    fg, sg = f[ii].cpu().numpy(), s[ii].cpu().numpy()
+    del f, s
+    torch.cuda.empty_cache()
+    f_ref, s_ref = zo.scan(spec, idx.astype(np.uint64))
+    parity.check(fg, sg, f_ref, s_ref, spec.samples, "fp32", "in-core past 2^32", small_n=True, volume=1.0)

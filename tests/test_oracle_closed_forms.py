@@ -170,3 +170,29 @@ def test_sigma_shrinks_as_inverse_sqrt_n():
     sig = np.array([zo.scan(base.with_(samples=1 << int(k)))[1] for k in ks])  # (len(ks), G)
     slope = np.polyfit(ks * np.log(2.0), np.log(sig).mean(axis=1), 1)[0]
     assert abs(slope + 0.5) < 0.02, slope
+
+
+def test_gauss_points_past_two_to_the_32():
+    # a 5e9-point grid: flat indices past 2^32 and the grid's last points
+    # decode to their parameters (the 64-bit C-order decode, written out
+    # here with numpy) and meet the exact integrals there
+    a1, a2 = np.linspace(0.1, 10, 100000), np.linspace(0.1, 10, 50000)
+    spec = ScanSpec("gauss", [a1, a2], np.zeros(3), np.ones(3), 2048, 19)
+    g = np.concatenate([np.arange(2**32 - 700, 2**32 + 700), np.arange(spec.G - 700, spec.G)])
+    f, s = zo.scan(spec, g.astype(np.uint64))
+    X = np.stack([a1[g // 50000], a2[g % 50000]], axis=1)
+    f_true, var = cf.exact(spec, X)
+    z = (f - f_true) / (cf.volume(spec) * np.sqrt(var / spec.samples))
+    ok, msg = cf.coverage_ok(z, "gauss past 2^32")
+    assert ok, msg
+
+
+def test_streams_differ_across_the_high_index_word():
+    # points g and g + 2^32 differ only in the counter's high index word;
+    # LINEAR ignores the parameters, so equal results would mean a dropped word
+    spec = ScanSpec("linear", [np.arange(2.0 ** 17), np.arange(2.0 ** 17)], np.zeros(2), np.ones(2),
+                    64, 3)
+    g = np.arange(200, dtype=np.uint64)
+    f0, _ = zo.scan(spec, g)
+    f1, _ = zo.scan(spec, g + np.uint64(2**32))
+    assert np.all(f0 != f1)
