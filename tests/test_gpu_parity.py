@@ -267,6 +267,10 @@ EDGE = [
     wl.ScanSpec("cosexp", [np.linspace(-1, 1, 3)] * 4, np.zeros(5), np.array([2.0, 1, 1, 1, 1]), 1001, 7),
     wl.ScanSpec("linear", [np.arange(257.0)], -np.ones(7), np.ones(7), 4097, 8),
     wl.ScanSpec("gauss", [np.linspace(0.1, 9, 70000)], np.zeros(2), np.ones(2), 33, 9),
+    # the largest shapes: 16 parameter axes (G = 2^16), and M = N = 8
+    wl.ScanSpec("sin_sum", [np.array([0.0, 0.5 + k / 16.0]) for k in range(16)], np.zeros(8),
+                np.ones(8), 33, 10),
+    wl.ScanSpec("gauss", [np.linspace(0.1, 9, 3)] * 8, np.zeros(8), np.ones(8), 257, 11),
 ]
 
 

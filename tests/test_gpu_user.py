@@ -21,6 +21,9 @@ WAVE = HEAD + ("  T s = p[1];\n  for (int k = 0; k < %d; ++k) s += (k + 1) * y[k
                "  return cos(x[0] * s) * exp(-p[0] * y[0] * y[0]) + p[2];\n}\n")
 PEAK = HEAD + ("  T q = 0;\n  for (int k = 0; k < %d; ++k) { T d = y[k] - x[k %% %d]; q += d * d; }\n"
                "  return T(1) / (p[0] + q);\n}\n")
+# the largest shape: all 16 parameters and 8 dimensions enter
+SUM16 = HEAD + ("  T s = T(0);\n  for (int k = 0; k < 16; ++k) s += x[k];\n"
+                "  for (int k = 0; k < 8; ++k) s += y[k];\n  return sin(s);\n}\n")
 PRODUCT = HEAD + ("  T r = T(1);\n  for (int k = 0; k < %d; ++k) r *= T(1) + x[0] * sin(y[k]);\n"
                   "  return r;\n}\n")
 
@@ -60,6 +63,8 @@ def _cases(precision):
     out.append(wl.ScanSpec("user", [], np.zeros(2), np.ones(2), 100003, 24, precision,
                            name="M0 one integral", source=WAVE.replace("x[0]", "T(2)") % 2,
                            params=np.array([1.0, 0.0, 0.0])))
+    out.append(wl.ScanSpec("user", [np.array([0.0, 0.5 + k / 16.0]) for k in range(16)], np.zeros(8),
+                           np.ones(8), 33, 25, precision, name="sum M16 N8", source=SUM16))
     return out
 
 

@@ -196,3 +196,17 @@ def test_streams_differ_across_the_high_index_word():
     f0, _ = zo.scan(spec, g)
     f1, _ = zo.scan(spec, g + np.uint64(2**32))
     assert np.all(f0 != f1)
+
+
+def test_sin_sum_sixteen_parameter_axes():
+    # the largest parameter count: 16 axes of two values each (G = 2^16);
+    # sampled points against the closed form at numpy's own C-order grid
+    axes = [np.array([0.0, 0.5 + k / 16.0]) for k in range(16)]
+    spec = ScanSpec("sin_sum", axes, np.zeros(8), np.ones(8), 1024, 10)
+    idx = np.sort(np.random.default_rng(5).choice(spec.G, 3000, replace=False))
+    f, s = zo.scan(spec, idx.astype(np.uint64))
+    X = cf.grid_points(spec)[idx]
+    f_true, var = cf.sin_sum_exact(spec, X)
+    z = (f - f_true) / (cf.volume(spec) * np.sqrt(var / spec.samples))
+    ok, msg = cf.coverage_ok(z, "sin_sum M=16")
+    assert ok, msg
