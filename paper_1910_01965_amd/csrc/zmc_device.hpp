@@ -342,11 +342,13 @@ template <typename T, int N> struct SinSum {
 template <typename T, int N> struct GaussUnit {
   T A[N], B[N];
   __device__ __forceinline__ T value(const T* t) const {
-    T q = (T)0;
+    // the first square is a plain product: fma(z, z, +0) would be the same
+    // value but a three-operand instruction, which cannot dual-issue
+    T q;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       const T z = fmaT(A[k], t[k], B[k]);
-      q = fmaT(z, z, q);
+      q = k == 0 ? z * z : fmaT(z, z, q);
     }
     if constexpr (sizeof(T) == 8) {
       return exp(-q);
@@ -391,11 +393,11 @@ template <typename T, int N> struct Gauss {
     return u;
   }
   __device__ __forceinline__ T value(const T* t) const {
-    T q = (T)0;
+    T q;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       const T y = fmaT(A[k], t[k], B[k]);
-      q = fmaT(c[k] * y, y, q);
+      q = k == 0 ? (c[k] * y) * y : fmaT(c[k] * y, y, q);
     }
     if constexpr (sizeof(T) == 8) {
       return exp(-q);
@@ -439,10 +441,15 @@ template <typename T, int N> struct CosExp {
       for (int k = 2; k < N; ++k) ph += fmaT(A[k], t[k], B[k]);
       return cos_turns(ph) * exp(nx3sq * y1 * y2) + x4;
     } else {
-      float ph = rest;
+      float ph;
+      if constexpr (N == 2) {
+        ph = fmaT(x1, y1, x2 * y2);  // no further terms: no zero addend
+      } else {
+        ph = rest;
 #pragma unroll
-      for (int k = 2; k < N; ++k) ph = fmaT(A[k], t[k], ph);
-      ph = fmaT(x1, y1, fmaT(x2, y2, ph));
+        for (int k = 2; k < N; ++k) ph = fmaT(A[k], t[k], ph);
+        ph = fmaT(x1, y1, fmaT(x2, y2, ph));
+      }
       const float e = __builtin_amdgcn_exp2f(nx3sq * y1 * y2);
       return fmaT(cos_turns(ph), e, x4);
     }

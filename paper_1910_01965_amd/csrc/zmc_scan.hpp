@@ -40,7 +40,9 @@ __device__ __forceinline__ void lane_groups(const Fam& fam, const Gen& gen, uint
     acc.add4(v);
     ++j;
   }
-  for (; j < jfull; ++j) {
+  // j <= jfull here; the inequality test keeps the (wave-uniform) loop
+  // control on the scalar unit, which has no unsigned 64-bit "less than"
+  for (; j != jfull; ++j) {
     T v[4];
     eval_group<Fam, T, N>(fam, j, gen, v);
     acc.add4(v);
