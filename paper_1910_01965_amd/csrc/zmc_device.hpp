@@ -198,14 +198,17 @@ __host__ __device__ __forceinline__ Words4 philox_block_pm(uint32_t b, const Phi
 // ---------------------------------------------------------------------------
 template <typename T> struct Unif;
 
+// FP64: the variate is the word itself, t = r (exact), and the affine
+// constants carry the scale and the half-step offset of u = (r + 1/2) 2^-32:
+// y = lo + h u = (h 2^-32) r + (lo + h 2^-33).  The power-of-two scalings are
+// exact; the one rounding of B moves y by at most half an ulp from
+// fma(h, u, lo), and the map costs a conversion and one fma per coordinate.
 template <> struct Unif<double> {
-  static __device__ __forceinline__ double t(uint32_t r) {
-    return ((double)r + 0.5) * 0x1p-32;
-  }
-  static constexpr double center = 0.5;
+  static __device__ __forceinline__ double t(uint32_t r) { return (double)r; }
   static __host__ __device__ inline void affine(double lo, double hi, double* A, double* B) {
-    *A = hi - lo;
-    *B = lo;
+    const double h = hi - lo;
+    *A = h * 0x1p-32;
+    *B = lo + h * 0x1p-33;
   }
 };
 
@@ -214,7 +217,6 @@ template <> struct Unif<float> {
     // (0x7F : r) >> 9 = 0x3F800000 | (r >> 9): a float in [1, 2)
     return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, r, 9u));
   }
-  static constexpr float center = 1.5f;
   static __host__ __device__ inline void affine(double lo, double hi, double* A, double* B) {
     *A = hi - lo;
     *B = lo - (hi - lo) * (1.0 - 0x1p-24);
