@@ -232,3 +232,14 @@ def test_range_scan_argument_checks(lib):
     assert lib.zmc_scan_range(d.ref, 3, 3, vp(f.ctypes.data), vp(f.ctypes.data), 0) == 1
     assert lib.zmc_scan_range(d.ref, 0, GOOD.G + 1, vp(f.ctypes.data), vp(f.ctypes.data), 0) == 1
     assert lib.zmc_scan_range(d.ref, 4, 2, vp(f.ctypes.data), vp(f.ctypes.data), 0) == 1
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    # no CPU fallback: every entry point of the binding needs the HIP library
+    monkeypatch.setattr(zmc, "_lib", None)
+    monkeypatch.setattr(zmc, "LIB_PATH", "/nonexistent/libzmc.so")
+    spec = wl.gauss_2p(points_per_axis=4, samples=8)
+    for call in (lambda: zmc.scan(spec), lambda: zmc.scan_host(spec), lambda: zmc.plan(spec),
+                 lambda: zmc.scan_chunked(spec), lambda: zmc.Batch([spec]), lambda: zmc.Server()):
+        with pytest.raises(RuntimeError, match="no fallback"):
+            call()
