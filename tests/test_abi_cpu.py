@@ -52,6 +52,7 @@ GOOD = wl.ScanSpec("gauss", [np.linspace(0.1, 10, 5), np.linspace(0.1, 10, 7)],
     (GOOD.with_(axes=[np.arange(1.0, 3.0)] * 4), 1),           # GAUSS needs M <= N
     (GOOD.with_(family="nope"), 1),
     (GOOD.with_(precision="fp16"), 1),
+    (GOOD.with_(axes=[np.zeros(0), np.linspace(0.1, 10, 7)]), 1),  # an empty axis (G = 0)
     (GOOD.with_(axes=[np.arange(2.0)] * 17), 1),               # M > 16
     (GOOD.with_(lo=np.zeros(17), hi=np.ones(17)), 1),          # N > 16
     (GOOD.with_(lo=np.zeros(12), hi=np.ones(12)), 4),          # N 9..16: unsupported
