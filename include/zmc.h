@@ -44,7 +44,8 @@ extern "C" {
 typedef enum zmc_status {
   ZMC_OK = 0,
   ZMC_E_INVALID = 1,     /* malformed descriptor or argument              */
-  ZMC_E_NOMEM = 2,       /* device or host allocation failed              */
+  ZMC_E_NOMEM = 2,       /* device or host allocation failed, or a buffer
+                            the call would size exceeds 2^56 bytes         */
   ZMC_E_DEVICE = 3,      /* a HIP call failed (no device, launch error)   */
   ZMC_E_UNSUPPORTED = 4, /* valid request this build does not implement   */
   ZMC_E_BUSY = 5         /* resource limit reached; retry later           */
@@ -141,13 +142,17 @@ zmc_status zmc_validate(const zmc_scan_desc* desc, uint64_t* grid_points);
 
 /* Host-only work decomposition that zmc_scan_device_ex would use with these
  * options (opts may be NULL).  Without opts->cu_count, queries the current
- * device's compute-unit count (ZMC_E_DEVICE if there is none). */
+ * device's compute-unit count (ZMC_E_DEVICE if there is none).  Explicit
+ * splits whose partials (16 B per point and piece) would exceed 2^56 bytes
+ * give ZMC_E_NOMEM; automatic plans keep them under 8 GiB. */
 zmc_status zmc_plan(const zmc_scan_desc* desc, const zmc_launch_opts* opts,
                     zmc_plan_info* out);
 
 /* Synchronous scan with host memory: stages desc->axis_vals to the device,
  * computes, copies f and sigma (G doubles each, C order) back into the
- * caller's host arrays.  On error the outputs are unspecified. */
+ * caller's host arrays.  On error the outputs are unspecified.  Grids whose
+ * f and sigma would exceed 2^56 bytes of staging give ZMC_E_NOMEM (use
+ * zmc_scan_chunked). */
 zmc_status zmc_scan(const zmc_scan_desc* desc, double* f, double* sigma);
 
 /* Asynchronous scan on `stream` with device-resident data: d_axis_vals holds

@@ -142,6 +142,10 @@ constexpr uint64_t kMaxGridX = (uint64_t)1 << 30;
 constexpr int kMaxSplits = 65535;
 constexpr uint64_t kMaxWorkspace = (uint64_t)8 << 30;
 constexpr uint64_t kDefaultChunk = (uint64_t)1 << 24;  // points per chunk of a chunked scan
+// Largest device allocation the entry points will size (64 PiB, far above any
+// device): products such as 16 x splits x G are checked against it before they
+// are formed, so that no size can wrap around 2^64.
+constexpr uint64_t kMaxBytes = (uint64_t)1 << 56;
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 zmc_status make_plan(const zmc_scan_desc* d, uint64_t G, const zmc_launch_opts* o, zmc::Plan* pl) {
@@ -184,6 +188,9 @@ zmc_status make_plan(const zmc_scan_desc* d, uint64_t G, const zmc_launch_opts* 
   if (splits > groups) splits = groups;
   const uint64_t gps = cdiv(groups, splits);
   splits = cdiv(groups, gps);  // no empty piece
+  if (splits > 1 && G > kMaxBytes / (16 * splits))
+    return fail(ZMC_E_NOMEM, "split partials of %llu points x %llu pieces exceed %llu bytes",
+                (unsigned long long)G, (unsigned long long)splits, (unsigned long long)kMaxBytes);
   pl->mode = mode;
   pl->block = block;
   pl->splits = (int)splits;
@@ -333,6 +340,9 @@ zmc_status zmc_scan(const zmc_scan_desc* desc, double* f, double* sigma) {
   if (st != ZMC_OK) return st;
   if (desc->M > 0 && desc->axis_vals == nullptr) return fail(ZMC_E_INVALID, "axis_vals is NULL with M > 0");
   if (f == nullptr || sigma == nullptr) return fail(ZMC_E_INVALID, "f or sigma is NULL");
+  if (G > kMaxBytes / 16)
+    return fail(ZMC_E_NOMEM, "f and sigma of %llu points exceed %llu bytes of device staging",
+                (unsigned long long)G, (unsigned long long)kMaxBytes);
   uint64_t total = 0;
   for (int l = 0; l < desc->M; ++l) total += (uint64_t)desc->axis_len[l];
   double *d_axis = nullptr, *d_out = nullptr;
@@ -414,6 +424,10 @@ zmc_status zmc_scan_range(const zmc_scan_desc* desc, uint64_t g_begin, uint64_t 
     return fail(ZMC_E_INVALID, "range [%llu, %llu) is empty or outside the grid of %llu points",
                 (unsigned long long)g_begin, (unsigned long long)g_end, (unsigned long long)G);
   const uint64_t R = g_end - g_begin;  // points of the range; f[i] is point g_begin + i
+  const uint64_t C = std::min<uint64_t>(R, chunk_points > 0 ? chunk_points : kDefaultChunk);
+  if (C > kMaxBytes / 32)
+    return fail(ZMC_E_NOMEM, "chunks of %llu points exceed %llu bytes of staging",
+                (unsigned long long)C, (unsigned long long)kMaxBytes);
   zmc::UserKernels uk;
   if (desc->family == ZMC_USER) {
     st = zmc::user_kernels(desc->integrand, desc->precision, desc->N, desc->M, &uk);
@@ -425,7 +439,6 @@ zmc_status zmc_scan_range(const zmc_scan_desc* desc, uint64_t g_begin, uint64_t 
   st = make_plan(desc, G, nullptr, &full);
   if (st != ZMC_OK) return st;
   const zmc_launch_opts fixed{full.mode, full.block, full.splits, 0, nullptr, nullptr};
-  const uint64_t C = std::min<uint64_t>(R, chunk_points > 0 ? chunk_points : kDefaultChunk);
   zmc::Plan cp;
   st = make_plan(desc, C, &fixed, &cp);
   if (st != ZMC_OK) return st;

@@ -1,5 +1,6 @@
 """The C ABI on the CPU: the library loads, exports every declared symbol,
 validates descriptors and plans work without touching a device."""
+import ctypes
 import os
 import re
 
@@ -244,3 +245,22 @@ def test_binding_fails_loudly_without_the_library(monkeypatch):
                  lambda: zmc.scan_chunked(spec), lambda: zmc.Batch([spec]), lambda: zmc.Server()):
         with pytest.raises(RuntimeError, match="no fallback"):
             call()
+
+
+def test_oversized_buffers_are_refused_before_any_device_call(lib):
+    # sizes that would wrap 2^64 if formed: refused with ZMC_E_NOMEM before
+    # any HIP call (on a machine without a GPU a HIP call would give
+    # ZMC_E_DEVICE instead)
+    big = wl.ScanSpec("sin_sum", [np.arange(2.0 ** 19)] * 3, np.zeros(2), np.ones(2), 1 << 20, 1,
+                      "fp32")                                        # G = 2^57
+    with pytest.raises(zmc.ZmcError) as ei:
+        zmc.plan(big, mode="point_major", splits=65535, cu_count=256)
+    assert ei.value.status == 2 and "split partials" in str(ei.value)
+    d = zmc.Desc(big)
+    f = np.zeros(4)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.zmc_scan(d.ref, f.ctypes.data_as(dp), f.ctypes.data_as(dp)) == 2
+    assert "staging" in lib.zmc_last_error().decode()
+    st = lib.zmc_scan_range(d.ref, 0, 1 << 56, ctypes.c_void_p(f.ctypes.data),
+                            ctypes.c_void_p(f.ctypes.data), 1 << 56)
+    assert st == 2 and "chunks" in lib.zmc_last_error().decode()
