@@ -357,7 +357,10 @@ typedef struct zmc_server_stats {
   uint64_t bytes_peak;
 } zmc_server_stats;
 
-/* Starts the scheduler thread on the current device. */
+/* Starts the scheduler thread on the current device.  submit, poll, wait
+ * and get_stats may be called from any number of threads at once; destroy
+ * must not overlap any other call on the same server, and the handle is
+ * invalid once it has returned. */
 zmc_status zmc_server_create(const zmc_server_opts* opts, zmc_server** out);
 
 /* Queues one scan; never waits for the GPU.  The descriptor and its host
@@ -379,7 +382,10 @@ zmc_status zmc_server_wait(zmc_server* server, uint64_t ticket, zmc_status* resu
 
 zmc_status zmc_server_get_stats(zmc_server* server, zmc_server_stats* stats);
 
-/* Finishes every submitted request, stops the thread, frees the server. */
+/* Finishes every submitted request (the queued ones included), stops the
+ * thread, frees the server.  Callers must first return from every other call
+ * on this server (a thread still blocked in zmc_server_wait would wake on
+ * freed memory). */
 zmc_status zmc_server_destroy(zmc_server* server);
 
 #ifdef __cplusplus
