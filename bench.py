@@ -9,7 +9,8 @@ lists and the output buffers are resident in HBM before the timed region.
 Prints ONE JSON line on stdout.  Extra fields: the FP64 path on the same
 workload, per-step latency percentiles, the roofline of the main kernel
 (VALU-bound; algorithmic lane-operations per sample stated in the design doc),
-and the CPU oracle timed on a bounded sample of the same workload.
+the CPU oracle timed on a bounded sample of the same workload (and of the
+other workloads), and the paper's own throughput figures as context.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -190,6 +191,61 @@ def cpu_baseline(spec, points, seed=0):
                       f"{dt:.1f} s",
             "host": {"cpu": model, "logical_cpus": os.cpu_count()},
             "full_grid_one_core_s_extrapolated": full_s}
+
+
+def cpu_baseline_others(seed=0):
+    """The oracle on one host core for the other workloads: the whole
+    1000-point plain FP64 scan, the 1e4-point subsample of the 1e8-point
+    COSEXP grid and one seeded point of each of the 512 batch scans, each
+    with its whole-workload single-core time extrapolated from the sample."""
+    from oracle import oracle as zo
+    from paper_1910_01965_amd import workloads as wl
+    out = {}
+    sp = wl.plain_fp64()
+    t0 = time.perf_counter()
+    zo.scan(sp)
+    dt = time.perf_counter() - t0
+    n = sp.G * sp.samples
+    out[sp.name] = {"sample": "the whole scan", "samples": n, "seconds": dt, "samples_per_s": n / dt}
+    sp = wl.cosexp_4p(precision="fp64")
+    idx = wl.cosexp_subsample()
+    t0 = time.perf_counter()
+    zo.scan(sp, idx)
+    dt = time.perf_counter() - t0
+    n = len(idx) * sp.samples
+    out["cosexp_4p_1e8pts_n4096"] = {
+        "sample": f"the {len(idx)}-point seeded subsample", "samples": n, "seconds": dt,
+        "samples_per_s": n / dt, "full_grid_one_core_s_extrapolated": sp.G * sp.samples / (n / dt)}
+    rng = np.random.default_rng(seed)
+    t_sum = t_full = 0.0
+    n = 0
+    for sp in wl.batched_512():
+        g = np.array([rng.integers(0, sp.G)], dtype=np.uint64)
+        t0 = time.perf_counter()
+        zo.scan(sp.with_(precision="fp64"), g)
+        dt = time.perf_counter() - t0
+        t_sum += dt
+        t_full += dt * sp.G
+        n += sp.samples
+    out["batched_512"] = {"sample": "one seeded point of each scan", "samples": n, "seconds": t_sum,
+                          "samples_per_s": n / t_sum, "full_batch_one_core_s_extrapolated": t_full}
+    return out
+
+
+def paper_context():
+    """The paper's own throughput on its own workloads and hardware, derived
+    from the times it prints (Table 1, Table 2): context, not a target."""
+    from paper_1910_01965_amd import replay
+    t1 = {f"M4_N{N}": 1e8 * 1e4 / replay.PAPER_TABLE1[(4, N)][3] for N in (1, 2, 3, 4)}
+    return {
+        "note": "the paper's runs: other workloads and hardware; samples/s derived from its times",
+        "table1": {"hardware": "1x NVIDIA Tesla V100 + Xeon Silver 4110",
+                   "workload": "Eq. (2) on [0,10]^N, x_l in {0..99} (1e8 points at M=4), 1e4 samples",
+                   "samples_per_s": t1},
+        "table2": {"workload": "Eq. (4), N=6, 1e8 points x 1e5 samples in 100 batches of 1e6 points",
+                   "v100_samples_per_s": 1e6 * 1e5 / replay.PAPER_TABLE2_V100_BATCH_S,
+                   "cluster": "4x K40m + 2x K80 + 1x V100 over 3 nodes",
+                   "cluster_samples_per_s": 1e8 * 1e5 / replay.PAPER_TABLE2_TOTAL_S}}
 
 
 def copy_probe(nbytes=1 << 30, reps=3):
@@ -419,8 +475,11 @@ def main():
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_points} points")
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_points)
+        log("cpu baseline: oracle on the other workloads")
+        out["cpu_baseline"]["other_workloads"] = cpu_baseline_others()
     else:
         out["cpu_baseline"] = None
+    out["paper_context"] = paper_context()
     print(json.dumps(out), flush=True)
 
 
