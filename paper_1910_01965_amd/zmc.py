@@ -345,6 +345,39 @@ def scan_range(spec, g_begin, g_end, chunk_points=0, f=None, sigma=None):
     return f, sigma
 
 
+def integrate(integrand, domain, parameters, samples, seed=0, precision="fp64", constants=None,
+              host=True):
+    """One parameter scan, stated as the paper states it (Sec. 2): f(x) is the
+    integral of g(y; x) over the box `domain` at every point x of the grid
+    spanned by the value lists `parameters`.
+
+    integrand:  a compiled-in family name ("sin_sum", "gauss", "cosexp") or
+                the HIP source of `integrand<T>(y, x, p)` (see include/zmc.h)
+    domain:     N pairs (lo, hi), one per integration variable
+    parameters: M sequences of values (the grid is their outer product)
+    constants:  up to 16 values p[] for a source integrand
+    host:       True: numpy arrays, streamed through host memory in chunks
+                (any grid size); False: float64 device tensors
+
+    Returns (f, sigma), each shaped (len(parameters[0]), ..., len(parameters[M-1]))."""
+    from . import workloads
+    box = np.asarray(domain, dtype=np.float64).reshape(-1, 2)
+    axes = [np.asarray(v, dtype=np.float64).ravel() for v in parameters]
+    if integrand in FAMILY and integrand != "user":
+        kw = dict(family=integrand)
+    else:
+        kw = dict(family="user", source=str(integrand),
+                  params=np.zeros(0) if constants is None else np.asarray(constants, dtype=np.float64))
+    spec = workloads.ScanSpec(axes=axes, lo=box[:, 0], hi=box[:, 1], samples=int(samples),
+                              seed=int(seed), precision=precision, name="integrate", **kw)
+    shape = spec.shape
+    if host:
+        f, s = scan_chunked(spec)
+    else:
+        f, s = scan(spec)
+    return f.reshape(shape), s.reshape(shape)
+
+
 def debug_words(seed, g, w0, count, stream=None):
     """Words w0 .. w0+count-1 of point g's stream from the device generator
     (int64 tensor holding the unsigned values)."""

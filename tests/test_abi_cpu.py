@@ -264,3 +264,13 @@ def test_oversized_buffers_are_refused_before_any_device_call(lib):
     st = lib.zmc_scan_range(d.ref, 0, 1 << 56, ctypes.c_void_p(f.ctypes.data),
                             ctypes.c_void_p(f.ctypes.data), 1 << 56)
     assert st == 2 and "chunks" in lib.zmc_last_error().decode()
+
+
+def test_integrate_front_end_rejects_bad_arguments(lib):
+    # checked by the library before any device use
+    with pytest.raises(zmc.ZmcError) as ei:
+        zmc.integrate("gauss", [(1.0, 0.0)] * 3, [[1.0, 2.0]], 64)      # lo >= hi
+    assert ei.value.status == 1
+    with pytest.raises(zmc.ZmcError) as ei:
+        zmc.integrate("not a function", [(0.0, 1.0)], [[1.0]], 64)     # source that does not compile
+    assert ei.value.status == 1

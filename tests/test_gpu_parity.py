@@ -323,3 +323,30 @@ def test_in_core_scan_past_two_to_the_32():
     torch.cuda.empty_cache()
     f_ref, s_ref = zo.scan(spec, idx.astype(np.uint64))
     parity.check(fg, sg, f_ref, s_ref, spec.samples, "fp32", "in-core past 2^32", small_n=True, volume=1.0)
+
+
+def test_integrate_front_end():
+    """zmc.integrate (integrand, domain, parameter lists) gives the results of
+    the descriptor entry points, shaped like the grid, on the host and on the
+    device; a source integrand with constants meets the oracle bar."""
+    zmc = _zmc()
+    ax = np.linspace(0.1, 10.0, 60)
+    spec = wl.gauss_2p(points_per_axis=60, samples=2048, precision="fp32")
+    f, s = zmc.integrate("gauss", [(0.0, 1.0)] * 3, [ax, ax], 2048, seed=42, precision="fp32")
+    assert f.shape == (60, 60) and s.shape == (60, 60) and isinstance(f, np.ndarray)
+    fa, sa = _run(spec)
+    assert np.array_equal(f.ravel(), fa) and np.array_equal(s.ravel(), sa)
+    fd, sd = zmc.integrate("gauss", [(0.0, 1.0)] * 3, [ax, ax], 2048, seed=42, precision="fp32",
+                           host=False)
+    assert fd.is_cuda and tuple(fd.shape) == (60, 60)
+    assert np.array_equal(fd.cpu().numpy(), f) and np.array_equal(sd.cpu().numpy(), s)
+    src = ("template <typename T> __device__ T integrand(const T* y, const T* x, const T* p) {\n"
+           "  return exp(-p[0] * x[0] * y[0] * y[0]) * cos(x[1] * y[1]);\n}\n")
+    a1, a2 = np.linspace(0.5, 3.0, 7), np.linspace(0.0, 2.0, 5)
+    f, s = zmc.integrate(src, [(-1.0, 1.0), (0.0, 2.0)], [a1, a2], 4099, seed=9, constants=[0.5])
+    ref = wl.ScanSpec("user", [a1, a2], np.array([-1.0, 0.0]), np.array([1.0, 2.0]), 4099, 9,
+                      "fp64", source=src, params=np.array([0.5]))
+    f_ref, s_ref = zo.scan(ref)
+    parity.check(f.ravel(), s.ravel(), f_ref, s_ref, ref.samples, "fp64", "integrate, source")
+    f0, s0 = zmc.integrate("sin_sum", [(0.0, 1.0)] * 2, [], 1000, seed=3)   # M = 0: one integral
+    assert f0.shape == () and np.isfinite(f0) and s0 > 0
