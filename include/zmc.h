@@ -159,7 +159,11 @@ zmc_status zmc_scan(const zmc_scan_desc* desc, double* f, double* sigma);
  * the concatenated value lists (sum L_l doubles; may be NULL when M = 0);
  * d_f and d_sigma receive G doubles each.  desc->axis_vals is not read.
  * Split partials, when the plan needs them, live in stream-ordered device
- * memory that is released on the same stream.  Returns after enqueueing. */
+ * memory that is released on the same stream.  Returns after enqueueing.
+ * The call may be recorded by stream capture into a caller's HIP graph
+ * (kernels plus, for split plans, graph memory nodes; no memset nodes); each
+ * replay recomputes the same results, provided the device has been used
+ * once (the compute-unit count is cached) before the capture begins. */
 zmc_status zmc_scan_device(const zmc_scan_desc* desc, const double* d_axis_vals,
                            double* d_f, double* d_sigma, void* stream);
 
