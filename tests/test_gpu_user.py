@@ -224,3 +224,43 @@ def test_user_integrands_in_the_server():
         assert np.array_equal(f.cpu().numpy(), fa.cpu().numpy()), sp.name
         assert np.array_equal(s.cpu().numpy(), sa.cpu().numpy()), sp.name
     srv.close()
+
+
+def test_a_variant_that_fails_to_compile_fails_alone():
+    """An integrand that compiles only in FP64: a single FP32 scan fails with
+    ZMC_E_INVALID and the compiler's message; in the server the FP32 request
+    fails at admission while the other requests, the FP64 use of the same
+    handle included, complete with their alone results; a batch holding it
+    is refused as a whole; the library stays usable."""
+    import torch
+    zmc = _zmc()
+    src = HEAD + '  static_assert(sizeof(T) == 8, "FP64 only");\n  return exp(-x[0] * y[0] * y[0]);\n}\n'
+    ok64 = wl.ScanSpec("user", [np.linspace(0.5, 2.0, 30)], np.zeros(1), np.ones(1), 1024, 3, "fp64",
+                       source=src)
+    bad32 = ok64.with_(precision="fp32")
+    with pytest.raises(zmc.ZmcError) as ei:
+        zmc.scan(bad32)
+    assert ei.value.status == 1 and "FP64 only" in str(ei.value)
+    g32 = wl.gauss_2p(points_per_axis=40, samples=2048, precision="fp32")
+    g64 = g32.with_(precision="fp64")
+    srv = zmc.Server(max_slots=4)
+    specs = [g32, bad32, ok64, g64]
+    tickets = [srv.submit(sp) for sp in specs]
+    assert [srv.wait(t)[0] for t in tickets] == [0, 1, 0, 0]
+    torch.cuda.synchronize()
+    for sp, t in zip(specs, tickets):
+        if sp is bad32:
+            continue
+        f, s = srv.outputs(t)
+        fa, sa = zmc.scan_batch([sp])[0]
+        assert np.array_equal(f.cpu().numpy(), fa.cpu().numpy())
+        assert np.array_equal(s.cpu().numpy(), sa.cpu().numpy())
+    assert srv.stats()["failed"] == 1 and srv.stats()["completed"] == 3
+    srv.close()
+    with pytest.raises(zmc.ZmcError) as ei:
+        zmc.Batch([g32, bad32])
+    assert ei.value.status == 1
+    f, s = zmc.scan(ok64)
+    torch.cuda.synchronize()
+    f_ref, s_ref = zo.scan(ok64)
+    parity.check(f.cpu().numpy(), s.cpu().numpy(), f_ref, s_ref, ok64.samples, "fp64", "after failures")
