@@ -37,6 +37,11 @@
 #include <stddef.h>
 #include <stdint.h>
 
+/* Environment: ZMC_LOG = 1 reports set-up events on stderr (tune-table
+ * loads, batch and server creation, run-time compiles), 2 also every plan and
+ * every server admission and completion; unset or 0, the library prints
+ * nothing.  ZMC_TUNE_TABLE names the tile-shape table (see the batch API). */
+
 #ifdef __cplusplus
 extern "C" {
 #endif

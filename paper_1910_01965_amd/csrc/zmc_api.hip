@@ -3,6 +3,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -31,6 +32,24 @@ zmc_status fail(zmc_status st, const char* fmt, ...) {
 zmc_status ok() {
   g_err[0] = '\0';
   return ZMC_OK;
+}
+
+int log_level() {
+  static const int level = [] {
+    const char* env = getenv("ZMC_LOG");
+    return (env && *env) ? atoi(env) : 0;
+  }();
+  return level;
+}
+
+void log(int level, const char* fmt, ...) {
+  if (log_level() < level) return;
+  char line[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(line, sizeof(line), fmt, ap);
+  va_end(ap);
+  fprintf(stderr, "[zmc] %s\n", line);
 }
 
 }  // namespace zmc
@@ -200,6 +219,11 @@ zmc_status make_plan(const zmc_scan_desc* d, uint64_t G, const zmc_launch_opts* 
   const uint64_t gx = (mode == ZMC_MODE_POINT_MAJOR) ? pl->point_blocks : G;
   pl->grid_x = gx < kMaxGridX ? gx : kMaxGridX;
   pl->workspace_bytes = splits > 1 ? 16 * splits * G : 0;
+  zmc::log(2, "plan: G=%llu n=%llu N=%d %s block=%d splits=%llu groups/piece=%llu blocks=%llu "
+           "workspace=%llu B", (unsigned long long)G, (unsigned long long)d->samples, d->N,
+           mode == ZMC_MODE_POINT_MAJOR ? "point-major" : "sample-major", block,
+           (unsigned long long)splits, (unsigned long long)gps,
+           (unsigned long long)(pl->grid_x * splits), (unsigned long long)pl->workspace_bytes);
   return ZMC_OK;
 }
 

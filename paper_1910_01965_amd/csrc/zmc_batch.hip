@@ -448,6 +448,9 @@ zmc_status zmc_batch_create(const zmc_scan_desc* scans, int32_t n_scans,
       return fail(ZMC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
     }
   }
+  zmc::log(1, "batch: %d scans, %d variants, %lld tiles, %llu samples, %zu B of device memory, %s",
+           n_scans, (int)b->variants.size(), (long long)b->info.tiles,
+           (unsigned long long)b->info.samples, total, b->use_graph ? "one graph" : "direct launches");
   *out = b;
   return ok();
 }

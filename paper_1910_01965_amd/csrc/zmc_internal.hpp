@@ -26,6 +26,13 @@ hipError_t launch_scan(const ScanParams& p, const Plan& plan, int precision, hip
                        hipEvent_t ev_begin, hipEvent_t ev_end);
 struct Tile;
 
+// Diagnostics on stderr, prefixed "[zmc] ", when the environment variable
+// ZMC_LOG is at least `level` (1: set-up events such as tune-table loads,
+// batch and server creation, run-time compiles; 2: also every plan and every
+// server admission and completion).  The level is read once per process.
+int log_level();
+void log(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
 // Host helpers shared by the single-scan and the batched entry points.
 zmc_status fail(zmc_status st, const char* fmt, ...);
 zmc_status ok();

@@ -122,6 +122,8 @@ zmc::Tile tile_of(const Request& r, uint64_t t) {
 
 void finish(zmc_server* s, const ReqPtr& r, zmc_status st) {
   r->latency = std::chrono::duration<double>(Clock::now() - r->t_submit).count();
+  zmc::log(2, "server: request %llu done, status %d, %.6f s after submit",
+           (unsigned long long)r->ticket, (int)st, r->latency);
   std::lock_guard<std::mutex> lk(s->mu);
   r->status = st;
   r->done = true;
@@ -361,6 +363,9 @@ void run(zmc_server* s) {
         break;
       }
       s->bytes_in_use += r->footprint;
+      zmc::log(2, "server: request %llu admitted (slot %d, %llu B, %llu tiles)",
+               (unsigned long long)r->ticket, r->slot, (unsigned long long)r->footprint,
+               (unsigned long long)r->total_tiles);
       s->active.push_back(r);
       admitted = progressed = true;
       std::lock_guard<std::mutex> lk(s->mu);
@@ -492,6 +497,9 @@ zmc_status zmc_server_create(const zmc_server_opts* opts, zmc_server** out) {
     release(s);
     return fail(ZMC_E_NOMEM, "could not start the scheduler thread");
   }
+  zmc::log(1, "server: budget %llu B, %d slots, %d tiles and %llu samples per slice, device %d",
+           (unsigned long long)o.hbm_budget_bytes, o.max_slots, o.slice_tiles,
+           (unsigned long long)o.slice_samples, s->device);
   *out = s;
   return ok();
 }

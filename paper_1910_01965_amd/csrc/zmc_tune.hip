@@ -60,7 +60,10 @@ void load() {
   memset(g_table.set, 0, sizeof(g_table.set));
   const std::string path = table_path();
   FILE* fh = fopen(path.c_str(), "r");
-  if (!fh) return;
+  if (!fh) {
+    zmc::log(1, "tune table %s not found: built-in tile shapes", path.c_str());
+    return;
+  }
   char line[512];
   int rows = 0;
   while (fgets(line, sizeof(line), fh)) {
@@ -78,6 +81,7 @@ void load() {
   }
   fclose(fh);
   if (rows > 0) g_table.source = path;
+  zmc::log(1, "tune table %s: %d rows", path.c_str(), rows);
 }
 
 }  // namespace

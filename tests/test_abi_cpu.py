@@ -274,3 +274,22 @@ def test_integrate_front_end_rejects_bad_arguments(lib):
     with pytest.raises(zmc.ZmcError) as ei:
         zmc.integrate("not a function", [(0.0, 1.0)], [[1.0]], 64)     # source that does not compile
     assert ei.value.status == 1
+
+
+def test_log_level_from_the_environment():
+    # ZMC_LOG=2 reports plans and set-up on stderr; unset, the library is silent
+    import subprocess
+    import sys
+    code = ("from paper_1910_01965_amd import zmc, workloads as wl\n"
+            "zmc.plan(wl.gauss_2p(), cu_count=256)\n"
+            "zmc.batch_plan(wl.batched_512()[:2], cu_count=256)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = {k: v for k, v in os.environ.items() if k != "ZMC_LOG"}
+    quiet = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True,
+                           text=True, timeout=120)
+    assert quiet.returncode == 0 and "[zmc]" not in quiet.stderr
+    loud = subprocess.run([sys.executable, "-c", code], cwd=root, env=dict(env, ZMC_LOG="2"),
+                          capture_output=True, text=True, timeout=120)
+    assert loud.returncode == 0
+    assert "[zmc] plan: G=1000000 n=16384 N=3 point-major" in loud.stderr
+    assert "[zmc] tune table" in loud.stderr
