@@ -293,3 +293,14 @@ def test_log_level_from_the_environment():
     assert loud.returncode == 0
     assert "[zmc] plan: G=1000000 n=16384 N=3 point-major" in loud.stderr
     assert "[zmc] tune table" in loud.stderr
+
+
+def test_c_program_uses_the_abi_without_python():
+    # tests/c/zmc_abi_check.c: include/zmc.h and libzmc.so from plain C
+    import subprocess
+    exe = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c", "zmc_abi_check")
+    if not os.path.exists(exe):
+        pytest.fail("tests/c/zmc_abi_check is not built (run __graft_entry__.build())")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "passed (host-only part)" in r.stdout
