@@ -6,12 +6,18 @@
  * error messages).  With --gpu it also runs, on the current device:
  *   - zmc_scan (host buffers) in both precisions against the oracle;
  *   - zmc_scan_range over a slice, bitwise equal to that slice of zmc_scan;
- *   - a run-time-compiled user integrand, against the same function in C.
+ *   - a run-time-compiled user integrand, against the same function in C;
+ *   - with device buffers from hipMalloc: zmc_scan_device (bitwise equal to
+ *     zmc_scan), zmc_scan_batch over three scans of different families and
+ *     precisions (against the oracle), and the server on the same three
+ *     (bitwise equal to the batch).
  * Exit status 0 when every check holds. */
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+#include <hip/hip_runtime_api.h>
 
 #include "zmc.h"
 #include "zmc_oracle.h"
@@ -50,6 +56,99 @@ static const char* kSource =
     "}\n";
 static double user_c(const double* y, const double* x, const double* p) {
   return exp(-p[0] * x[0] * y[0] * y[0]) * cos(x[1] * y[1] + y[2]);
+}
+
+#define NS 3
+
+/* Three scans: the Gaussian grid in FP32, a one-parameter SIN_SUM scan in
+ * FP64 on [0,1]^4, and a 5^4-point COSEXP grid in FP32 with a ragged sample
+ * count; all through device buffers. */
+static void device_checks(const double* gauss_vals, const int64_t* gauss_len) {
+  static double sin_vals[50], cos_vals[20];
+  static int64_t sin_len[1] = {50}, cos_len[4] = {5, 5, 5, 5};
+  for (int i = 0; i < 50; ++i) sin_vals[i] = i / 49.0;
+  for (int l = 0; l < 4; ++l)
+    for (int i = 0; i < 5; ++i) cos_vals[5 * l + i] = -1.0 + 0.5 * i;
+  static double lo3[3] = {0, 0, 0}, hi3[3] = {1, 1, 1}, lo4[4] = {0, 0, 0, 0}, hi4[4] = {1, 1, 1, 1};
+  static double lo2[2] = {0, 0}, hi2[2] = {2, 1};
+  zmc_scan_desc sc[NS];
+  memset(sc, 0, sizeof(sc));
+  sc[0].M = 2; sc[0].N = 3; sc[0].axis_len = gauss_len; sc[0].axis_vals = gauss_vals;
+  sc[0].lo = lo3; sc[0].hi = hi3; sc[0].family = ZMC_GAUSS; sc[0].precision = ZMC_FP32_MERGE64;
+  sc[0].samples = 4099; sc[0].seed = 42;
+  sc[1].M = 1; sc[1].N = 4; sc[1].axis_len = sin_len; sc[1].axis_vals = sin_vals;
+  sc[1].lo = lo4; sc[1].hi = hi4; sc[1].family = ZMC_SIN_SUM; sc[1].precision = ZMC_FP64;
+  sc[1].samples = 2048; sc[1].seed = 7;
+  sc[2].M = 4; sc[2].N = 2; sc[2].axis_len = cos_len; sc[2].axis_vals = cos_vals;
+  sc[2].lo = lo2; sc[2].hi = hi2; sc[2].family = ZMC_COSEXP; sc[2].precision = ZMC_FP32_MERGE64;
+  sc[2].samples = 1001; sc[2].seed = 9;
+  const int fam_o[NS] = {ZMC_ORACLE_GAUSS, ZMC_ORACLE_SIN_SUM, ZMC_ORACLE_COSEXP};
+  uint64_t G[NS];
+  double *d_f[NS], *d_s[NS], *d_f2[NS], *d_s2[NS];
+  double *h_f[NS], *h_s[NS], *h_f2[NS], *h_s2[NS], *r_f[NS], *r_s[NS];
+  for (int i = 0; i < NS; ++i) {
+    expect(zmc_validate(&sc[i], &G[i]) == ZMC_OK, "device scans: valid descriptor");
+    const size_t b = G[i] * sizeof(double);
+    expect(hipMalloc((void**)&d_f[i], b) == hipSuccess && hipMalloc((void**)&d_s[i], b) == hipSuccess &&
+               hipMalloc((void**)&d_f2[i], b) == hipSuccess && hipMalloc((void**)&d_s2[i], b) == hipSuccess,
+           "hipMalloc of the outputs");
+    h_f[i] = malloc(b); h_s[i] = malloc(b); h_f2[i] = malloc(b); h_s2[i] = malloc(b);
+    r_f[i] = malloc(b); r_s[i] = malloc(b);
+    zmc_oracle_spec o;
+    memset(&o, 0, sizeof(o));
+    o.M = sc[i].M; o.N = sc[i].N; o.axis_len = sc[i].axis_len; o.axis_vals = sc[i].axis_vals;
+    o.lo = sc[i].lo; o.hi = sc[i].hi; o.family = fam_o[i]; o.samples = sc[i].samples;
+    o.seed = sc[i].seed;
+    expect(zmc_oracle_scan(&o, NULL, (int64_t)G[i], r_f[i], r_s[i]) == 0, "oracle scan");
+  }
+  /* one batch, the library staging the lists */
+  expect(zmc_scan_batch(sc, NS, NULL, d_f, d_s, NULL) == ZMC_OK, "zmc_scan_batch of three scans");
+  for (int i = 0; i < NS; ++i) {
+    hipMemcpy(h_f[i], d_f[i], G[i] * 8, hipMemcpyDeviceToHost);
+    hipMemcpy(h_s[i], d_s[i], G[i] * 8, hipMemcpyDeviceToHost);
+    const int fp64 = sc[i].precision == ZMC_FP64;
+    char what[64];
+    snprintf(what, sizeof(what), "batched scan %d vs oracle", i);
+    compare(what, h_f[i], h_s[i], r_f[i], r_s[i], (int)G[i], (double)sc[i].samples,
+            fp64 ? 1e-12 : 2e-5, fp64 ? 1e-12 : 1e-3);
+  }
+  /* the server on the same scans: bitwise the batch's results */
+  zmc_server* srv = NULL;
+  expect(zmc_server_create(NULL, &srv) == ZMC_OK, "zmc_server_create");
+  uint64_t t[NS];
+  for (int i = 0; i < NS; ++i)
+    expect(zmc_server_submit(srv, &sc[i], NULL, d_f2[i], d_s2[i], &t[i]) == ZMC_OK, "zmc_server_submit");
+  for (int i = 0; i < NS; ++i) {
+    zmc_status st = ZMC_E_DEVICE;
+    double lat = -1.0;
+    expect(zmc_server_wait(srv, t[i], &st, &lat) == ZMC_OK && st == ZMC_OK && lat >= 0.0,
+           "zmc_server_wait: done");
+  }
+  expect(zmc_server_destroy(srv) == ZMC_OK, "zmc_server_destroy");
+  int same = 1;
+  for (int i = 0; i < NS; ++i) {
+    hipMemcpy(h_f2[i], d_f2[i], G[i] * 8, hipMemcpyDeviceToHost);
+    hipMemcpy(h_s2[i], d_s2[i], G[i] * 8, hipMemcpyDeviceToHost);
+    same = same && memcmp(h_f2[i], h_f[i], G[i] * 8) == 0 && memcmp(h_s2[i], h_s[i], G[i] * 8) == 0;
+  }
+  expect(same, "server results equal the batch's bit for bit");
+  /* zmc_scan_device with lists on the device: bitwise zmc_scan */
+  double* d_axis = NULL;
+  expect(hipMalloc((void**)&d_axis, 50 * 8) == hipSuccess &&
+             hipMemcpy(d_axis, sin_vals, 50 * 8, hipMemcpyHostToDevice) == hipSuccess,
+         "lists on the device");
+  expect(zmc_scan_device(&sc[1], d_axis, d_f2[1], d_s2[1], NULL) == ZMC_OK &&
+             hipDeviceSynchronize() == hipSuccess, "zmc_scan_device");
+  hipMemcpy(h_f2[1], d_f2[1], G[1] * 8, hipMemcpyDeviceToHost);
+  hipMemcpy(h_s2[1], d_s2[1], G[1] * 8, hipMemcpyDeviceToHost);
+  expect(zmc_scan(&sc[1], h_f[1], h_s[1]) == ZMC_OK, "zmc_scan of the same scan");
+  expect(memcmp(h_f2[1], h_f[1], G[1] * 8) == 0 && memcmp(h_s2[1], h_s[1], G[1] * 8) == 0,
+         "zmc_scan_device equals zmc_scan bit for bit");
+  (void)hipFree(d_axis);
+  for (int i = 0; i < NS; ++i) {
+    (void)hipFree(d_f[i]); (void)hipFree(d_s[i]); (void)hipFree(d_f2[i]); (void)hipFree(d_s2[i]);
+    free(h_f[i]); free(h_s[i]); free(h_f2[i]); free(h_s2[i]); free(r_f[i]); free(r_s[i]);
+  }
 }
 
 int main(int argc, char** argv) {
@@ -129,6 +228,7 @@ int main(int argc, char** argv) {
   expect(zmc_scan(&d, f, s) == ZMC_OK, "zmc_scan, user integrand FP64");
   compare("user integrand FP64 vs oracle", f, s, fr, sr, G_ALL, (double)d.samples, 1e-12, 1e-12);
   expect(zmc_integrand_destroy(h) == ZMC_OK, "zmc_integrand_destroy");
+  device_checks(vals, len);
   printf("%s\n", failures ? "FAILED" : "passed");
   return failures ? 1 : 0;
 }

@@ -1,6 +1,8 @@
 """The C ABI from plain C on the GPU (needs an MI355X): tests/c/zmc_abi_check
-runs host-memory scans in both precisions, a range scan and a run-time
-user integrand, and checks them against the oracle linked into it."""
+runs host-memory scans in both precisions, a range scan, a run-time user
+integrand, and (with hipMalloc'd buffers) a device scan, a three-scan batch
+and the server, checked against the oracle linked into it and against each
+other bit for bit."""
 import os
 import subprocess
 
