@@ -152,3 +152,29 @@ def test_shutdown_drains_pending_requests():
         f, s = srv.outputs(t)
         fa, sa = _alone(sp)
         assert np.array_equal(f.cpu().numpy(), fa) and np.array_equal(s.cpu().numpy(), sa)
+
+
+def test_one_slot_serves_in_arrival_order():
+    """With one slot the server admits requests in submission order: each
+    completes after the one before it (latencies, measured from each one's
+    submission, do not decrease for requests submitted together), poll agrees
+    with wait, and the statistics count every request once (the pending and
+    active gauges are refreshed by the scheduler loop after the wake-up, so
+    they are not read here)."""
+    zmc = _zmc()
+    specs = _requests(8, seed=11, max_samples=1 << 12)
+    srv = zmc.Server(max_slots=1)
+    tickets = [srv.submit(sp) for sp in specs]
+    lat = []
+    for t in tickets:
+        st, l = srv.wait(t)
+        assert st == 0
+        done, st2, l2 = srv.poll(t)
+        assert done and st2 == 0 and l2 == l
+        lat.append(l)
+    _say(f"one-slot latencies {['%.4f' % x for x in lat]}")
+    assert all(b >= a for a, b in zip(lat, lat[1:]))
+    stats = srv.stats()
+    assert stats["submitted"] == stats["admitted"] == stats["completed"] == len(specs)
+    assert stats["failed"] == 0
+    srv.close()
