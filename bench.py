@@ -260,6 +260,29 @@ def copy_probe(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def valu_probe(blocks=65536, iters=512, reps=3):
+    """The VALU calibration load (eight independent FMA chains per lane):
+    rocprofv3 VALU counters of its dispatches should read ~100 % issue-busy,
+    which checks the busy fraction reported for the scan kernels."""
+    import torch
+    from paper_1910_01965_amd import zmc
+    zmc.debug_valu_probe(blocks, iters)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        zmc.debug_valu_probe(blocks, iters)
+        b.record()
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    fmas = 64.0 * iters * blocks * 256
+    t = min(ms) / 1e3
+    print(json.dumps({"valu_probe": {"blocks": blocks, "iters": iters, "fma_lanes": fmas,
+                                     "ms": min(ms), "fma_lane_per_s": fmas / t,
+                                     "vs_single_issue_peak": fmas / t / (VALU_PEAK / 2)}}), flush=True)
+
+
 USER_GAUSS = ("template <typename T> __device__ T integrand(const T* y, const T* x, const T* p) {\n"
               "  return exp(-(x[0] * y[0] * y[0] + x[1] * y[1] * y[1] + y[2] * y[2]));\n}\n")
 
@@ -372,9 +395,14 @@ def main():
                     help="arrival window of the serving runs (the full workload is 60 s)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only run the FMA-chain load (VALU counter calibration)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.valu_probe:
+        valu_probe()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the scan shards by "

@@ -205,6 +205,15 @@ zmc_status zmc_scan_device_ex(const zmc_scan_desc* desc, const double* d_axis_va
 zmc_status zmc_debug_words(uint64_t seed, uint64_t g, uint64_t w0, int64_t count,
                            uint32_t* d_out, void* stream);
 
+/* Diagnostics: a calibration load for the VALU counters (not part of the
+ * method).  `blocks` blocks of 256 threads each run `iters` iterations of
+ * eight steps of eight independent FP32 multiply-add chains (64 x iters FMAs
+ * per lane) and
+ * write one float per thread to d_out (blocks x 256 floats, device memory).
+ * A launch that fills the device should read as ~100 % issue-busy in the
+ * counters used for the scan kernels.  Asynchronous on `stream`. */
+zmc_status zmc_debug_valu_probe(int32_t blocks, int64_t iters, float* d_out, void* stream);
+
 /* Debug: integrand values g(y_s; x_g) for samples s = s0 .. s0+count-1 of
  * grid point g, computed by the device sampler and integrand in the
  * descriptor's precision and widened to FP64, into d_out (count doubles). */

@@ -401,6 +401,15 @@ zmc_status zmc_debug_words(uint64_t seed, uint64_t g, uint64_t w0, int64_t count
   return ok();
 }
 
+zmc_status zmc_debug_valu_probe(int32_t blocks, int64_t iters, float* d_out, void* stream) {
+  if (blocks < 1 || blocks > (1 << 20)) return fail(ZMC_E_INVALID, "blocks = %d outside 1..2^20", blocks);
+  if (iters < 1) return fail(ZMC_E_INVALID, "iters = %lld < 1", (long long)iters);
+  if (d_out == nullptr) return fail(ZMC_E_INVALID, "d_out is NULL");
+  hipError_t e = zmc::launch_valu_probe(blocks, iters, d_out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(ZMC_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
 zmc_status zmc_debug_values(const zmc_scan_desc* desc, const double* d_axis_vals, uint64_t g,
                             uint64_t s0, int64_t count, double* d_out, void* stream) {
   uint64_t G = 0;

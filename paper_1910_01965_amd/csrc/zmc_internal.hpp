@@ -69,6 +69,7 @@ hipError_t launch_merge_batch(const ScanParams* scans, const uint32_t* merge_sca
 hipError_t launch_debug_words(uint64_t seed, uint64_t g, uint64_t w0, int64_t count,
                               uint32_t* out, hipStream_t stream);
 hipError_t launch_merge_splits(const ScanParams& p, hipStream_t stream);
+hipError_t launch_valu_probe(int32_t blocks, int64_t iters, float* out, hipStream_t stream);
 
 // Kernels of a user integrand for one (precision, N, M), built on first use.
 struct UserKernels {

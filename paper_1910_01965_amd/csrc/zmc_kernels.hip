@@ -38,6 +38,31 @@ __global__ void k_debug_words(uint64_t seed, uint64_t g, uint64_t w0, int64_t co
   out[i] = lane == 0 ? r.r[0] : lane == 1 ? r.r[1] : lane == 2 ? r.r[2] : r.r[3];
 }
 
+// Calibration load for the VALU counters: eight independent FP32 multiply-add
+// chains per lane, 64 multiply-adds per loop trip (the loop control is
+// wave-uniform, on the scalar unit), so a full launch keeps every SIMD's VALU
+// issue busy.
+__global__ __launch_bounds__(256) void k_valu_probe(int64_t iters, float* out) {
+  const float b = 0.999f + 1e-9f * (float)(threadIdx.x & 7);
+  const float c = 1e-3f;
+  float a0 = 1e-3f * (float)threadIdx.x, a1 = a0 + 1.0f, a2 = a0 + 2.0f, a3 = a0 + 3.0f;
+  float a4 = a0 + 4.0f, a5 = a0 + 5.0f, a6 = a0 + 6.0f, a7 = a0 + 7.0f;
+  for (int64_t i = 0; i != iters; ++i) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a0 = __builtin_fmaf(a0, b, c);
+    a1 = __builtin_fmaf(a1, b, c);
+    a2 = __builtin_fmaf(a2, b, c);
+    a3 = __builtin_fmaf(a3, b, c);
+    a4 = __builtin_fmaf(a4, b, c);
+    a5 = __builtin_fmaf(a5, b, c);
+    a6 = __builtin_fmaf(a6, b, c);
+      a7 = __builtin_fmaf(a7, b, c);
+    }
+  }
+  out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
+}
+
 namespace {
 
 template <typename T, class Fn>
@@ -122,6 +147,11 @@ hipError_t launch_debug_words(uint64_t seed, uint64_t g, uint64_t w0, int64_t co
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_debug_words, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
                      seed, g, w0, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_valu_probe(int32_t blocks, int64_t iters, float* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_valu_probe, dim3((unsigned)blocks), dim3(256), 0, stream, iters, out);
   return hipGetLastError();
 }
 

@@ -27,7 +27,8 @@ EXPORTS = ("zmc_last_error", "zmc_version", "zmc_validate", "zmc_plan", "zmc_sca
            "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch", "zmc_tune_source",
            "zmc_server_create", "zmc_server_submit", "zmc_server_poll", "zmc_server_wait",
            "zmc_server_get_stats", "zmc_server_destroy", "zmc_integrand_create",
-           "zmc_integrand_log", "zmc_integrand_destroy", "zmc_scan_chunked", "zmc_scan_range")
+           "zmc_integrand_log", "zmc_integrand_destroy", "zmc_scan_chunked", "zmc_scan_range",
+           "zmc_debug_valu_probe")
 
 
 class ZmcError(RuntimeError):
@@ -121,6 +122,7 @@ def load():
                                         ctypes.c_int64, vp, vp]
         lib.zmc_debug_values.argtypes = [descp, vp, ctypes.c_uint64, ctypes.c_uint64,
                                          ctypes.c_int64, vp, vp]
+        lib.zmc_debug_valu_probe.argtypes = [ctypes.c_int32, ctypes.c_int64, vp, vp]
         ptrs = ctypes.POINTER(ctypes.c_void_p)
         lib.zmc_batch_default_opts.argtypes = [ctypes.POINTER(BatchOpts)]
         lib.zmc_batch_default_opts.restype = None
@@ -376,6 +378,16 @@ def integrate(integrand, domain, parameters, samples, seed=0, precision="fp64", 
     else:
         f, s = scan(spec)
     return f.reshape(shape), s.reshape(shape)
+
+
+def debug_valu_probe(blocks, iters, stream=None):
+    """Launch the VALU calibration load (64 x iters FMAs per lane, blocks x 256
+    lanes) on `stream`; returns its float32 output tensor."""
+    import torch
+    out = torch.empty(int(blocks) * 256, dtype=torch.float32, device="cuda")
+    _check(load().zmc_debug_valu_probe(int(blocks), int(iters), ctypes.c_void_p(out.data_ptr()),
+                                       _stream_ptr(stream)))
+    return out
 
 
 def debug_words(seed, g, w0, count, stream=None):

@@ -350,3 +350,11 @@ def test_integrate_front_end():
     parity.check(f.ravel(), s.ravel(), f_ref, s_ref, ref.samples, "fp64", "integrate, source")
     f0, s0 = zmc.integrate("sin_sum", [(0.0, 1.0)] * 2, [], 1000, seed=3)   # M = 0: one integral
     assert f0.shape == () and np.isfinite(f0) and s0 > 0
+
+
+def test_valu_probe_runs():
+    import torch
+    out = _zmc().debug_valu_probe(64, 100)
+    torch.cuda.synchronize()
+    v = out.cpu().numpy()
+    assert v.shape == (64 * 256,) and np.all(np.isfinite(v)) and np.all(v > 0)
