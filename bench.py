@@ -145,7 +145,14 @@ def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=32, compare_p
         if ta > now:
             time.sleep(ta - now)
         tickets.append(srv.submit(sp))
-    lat = np.array([srv.wait(t)[1] for t in tickets])
+    lat = []
+    t_say = time.perf_counter()
+    for i, t in enumerate(tickets):
+        lat.append(srv.wait(t)[1])
+        if time.perf_counter() - t_say > 15.0:  # progress of long runs
+            log(f"  serving: {i + 1}/{n_req} requests done, {time.perf_counter() - t0:.0f} s")
+            t_say = time.perf_counter()
+    lat = np.array(lat)
     t_all = time.perf_counter() - t0
     stats = srv.stats()
     srv.close()
@@ -161,8 +168,11 @@ def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=32, compare_p
         axes = [zmc.axis_tensor(sp) for sp in specs]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for (f, s), sp, a in zip(outs, specs, axes):
+        for i, ((f, s), sp, a) in enumerate(zip(outs, specs, axes)):
             zmc.scan_device(sp, a, f, s)
+            if (i + 1) % 1000 == 0:  # progress of long runs
+                torch.cuda.synchronize()
+                log(f"  plain launches: {i + 1}/{n_req}, {time.perf_counter() - t0:.0f} s")
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
         out["plain_back_to_back"] = total / t_plain
