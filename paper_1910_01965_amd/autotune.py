@@ -17,8 +17,6 @@ import os
 import sys
 import time
 
-import numpy as np
-
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tune_table.txt")
 PM_CANDIDATES = (128, 256, 512, 1024, 2048, 4096, 8192)

@@ -64,7 +64,6 @@ constexpr int kBlock = zmc::kTileBlock;
 constexpr uint64_t kMaxTiles = (uint64_t)1 << 31;
 constexpr size_t kAlign = 256;
 
-uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // One persistent kernel per key: (precision, family, N) for the compiled-in

@@ -7,7 +7,6 @@ to a standard normal at every grid point and independent across points
 calculus (closed_forms.py), not from the oracle.
 """
 import numpy as np
-import pytest
 
 from oracle import oracle as zo
 from paper_1910_01965_amd.workloads import ScanSpec, plain_fp64, gauss_2p, cosexp_4p
