@@ -9,8 +9,13 @@
 
 namespace zmc {
 
+// Waves per SIMD asked of the point-major and batch kernels.  FP32 with
+// N >= 4 runs faster at 8 (the compiler then keeps 64 VGPRs and spills a few
+// set-up values); at N <= 3, and in FP64, its own choice is faster.
+template <typename T, int N> constexpr int kMinWaves = (sizeof(T) == 4 && N >= 4) ? 8 : 1;
+
 template <class Fam, typename T, int N>
-__global__ __launch_bounds__(256) void k_point_major(ScanParams p) {
+__global__ __launch_bounds__(256, (kMinWaves<T, N>)) void k_point_major(ScanParams p) {
   point_major_body<Fam, T, N>(p);
 }
 
@@ -25,7 +30,7 @@ __global__ __launch_bounds__(1024) void k_sample_major(ScanParams p) {
 // counter (tiles are sorted longest first) and exit once the table is
 // exhausted; every block reaches that exit.
 template <class Fam, typename T, int N>
-__global__ __launch_bounds__(256) void k_batch(const ScanParams* __restrict__ scans,
+__global__ __launch_bounds__(256, (kMinWaves<T, N>)) void k_batch(const ScanParams* __restrict__ scans,
                                                const Tile* __restrict__ tiles, uint32_t begin,
                                                uint32_t end, uint32_t* counter) {
   __shared__ uint32_t next;
