@@ -37,7 +37,7 @@ VALU_PEAK = 256 * 128 * 2.4e9
 # HBM bytes per dispatch of the main kernel on the default workload, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy (profiles/), keyed
 # by the library version they were taken with; null for any other build.
-TRAFFIC_BYTES = {"zmc 0.6 gfx950": 0.412e6 + 144.0e6}
+TRAFFIC_BYTES = {"zmc 0.7 gfx950": 0.412e6 + 144.0e6}
 
 
 def valu_ops_per_sample(family, N):
