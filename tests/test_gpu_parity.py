@@ -171,9 +171,10 @@ def test_gauss_full_grid_every_point():
         _say(msg)
 
 
-def test_cosexp_full_grid_subsample():
-    spec = wl.cosexp_4p(precision="fp32")
-    _say(f"scan {spec.name} full grid fp32")
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_cosexp_full_grid_subsample(precision):
+    spec = wl.cosexp_4p(precision=precision)
+    _say(f"scan {spec.name} full grid {precision}")
     import torch
     f, s = _zmc().scan(spec)
     idx = wl.cosexp_subsample()
@@ -182,7 +183,7 @@ def test_cosexp_full_grid_subsample():
     assert bool(torch.isfinite(f).all()) and bool(torch.isfinite(s).all())
     del f, s
     f_ref, s_ref = zo.scan(spec, idx)
-    _, _, msg = parity.check(fs, ss, f_ref, s_ref, spec.samples, "fp32", spec.name + " subsample")
+    _, _, msg = parity.check(fs, ss, f_ref, s_ref, spec.samples, precision, spec.name + " subsample")
     _say(msg)
 
 
