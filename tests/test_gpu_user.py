@@ -264,3 +264,24 @@ def test_a_variant_that_fails_to_compile_fails_alone():
     torch.cuda.synchronize()
     f_ref, s_ref = zo.scan(ok64)
     parity.check(f.cpu().numpy(), s.cpu().numpy(), f_ref, s_ref, ok64.samples, "fp64", "after failures")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_user_gaussian_at_the_benchmark_size(precision):
+    """The Gaussian written as a user integrand on the full 1000 x 1000 grid
+    with 2^14 samples, the configuration the benchmark times: 300 sampled
+    points and both corners against the oracle."""
+    import torch
+    zmc = _zmc()
+    src = HEAD + "  return exp(-(x[0] * y[0] * y[0] + x[1] * y[1] * y[1] + y[2] * y[2]));\n}\n"
+    spec = wl.gauss_2p(precision=precision).with_(family="user", source=src)
+    _say(f"user gaussian 1e6 points {precision}")
+    f, s = zmc.scan(spec)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(2).choice(spec.G, 300, replace=False))
+    idx = np.concatenate([[0, spec.G - 1], idx]).astype(np.uint64)
+    ti = torch.from_numpy(idx.astype(np.int64)).cuda()
+    fs, ss = f[ti].cpu().numpy(), s[ti].cpu().numpy()
+    f_ref, s_ref = zo.scan(spec, idx)
+    _, _, msg = parity.check(fs, ss, f_ref, s_ref, spec.samples, precision, "user gaussian 1e6")
+    _say(msg)
