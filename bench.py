@@ -348,9 +348,7 @@ def chunked_run(big=False):
     import torch
     from paper_1910_01965_amd import workloads as wl
     from paper_1910_01965_amd import zmc
-    axes = [np.linspace(0.0, 1.0, 30)] * 3 + [np.linspace(0.0, 0.5, 10)] * 3 + [np.arange(7.0)]
-    spec = wl.ScanSpec("sin_sum", axes, np.zeros(5), np.ones(5), 1024, 5, "fp32",
-                       name="boltzmann_shape_30^3x10^3x7_N5_n1024")
+    spec = wl.boltzmann_shape()
     res = {"workload": spec.name, "grid_points": spec.G, "samples_per_point": spec.samples}
     r = time_path(spec, 2, 1)
     dev = r["wall_s"] / 2

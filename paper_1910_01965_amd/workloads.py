@@ -15,6 +15,8 @@ COSEXP are the two further benchmark integrands):
                   y in [0,2]x[0,1], 4096 samples, seed 42
   batched_512     512 scans with log-uniform grid sizes in [1e3,1e6], N in
                   2..8, samples in {2^10..2^18}, family uniform, seeds 0..511
+  boltzmann_shape 30^3 x 10^3 x 7 = 1.89e8 points, SIN_SUM over the seven
+                  parameters, y in [0,1]^5, 1024 samples, seed 5 (out-of-core)
 """
 from dataclasses import dataclass, field
 from typing import List
@@ -93,6 +95,17 @@ def cosexp_4p(points_per_axis=100, samples=4096, seed=42, precision="fp32"):
     return ScanSpec("cosexp", [ax, ax.copy(), ax.copy(), ax.copy()], np.array([0.0, 0.0]),
                     np.array([2.0, 1.0]), samples, seed, precision,
                     name=f"cosexp_4p_{points_per_axis}^4_N2_n{samples}")
+
+
+def boltzmann_shape(samples=1024, seed=5, precision="fp32"):
+    """A grid shaped like the paper's Boltzmann application (Sec. 3.3): three
+    momentum components with 30 values, three with 10, and 7 species, i.e.
+    1.89e8 points, over a 5-dimensional integral; SIN_SUM over the seven
+    parameters stands in for the collision integrand, which the paper does
+    not give."""
+    axes = [np.linspace(0.0, 1.0, 30)] * 3 + [np.linspace(0.0, 0.5, 10)] * 3 + [np.arange(7.0)]
+    return ScanSpec("sin_sum", axes, np.zeros(5), np.ones(5), samples, seed, precision,
+                    name=f"boltzmann_shape_30^3x10^3x7_N5_n{samples}")
 
 
 def cosexp_subsample(G=10**8, k=10**4, seed=42):

@@ -153,3 +153,23 @@ def test_range_past_two_to_the_32(precision):
     fl, sl = zmc.scan_range(spec, spec.G - 1000, spec.G)
     f_ref, s_ref = zo.scan(spec, np.arange(spec.G - 1000, spec.G, dtype=np.uint64))
     parity.check(fl, sl, f_ref, s_ref, spec.samples, precision, "last points", small_n=True)
+
+
+def test_boltzmann_shaped_grid_at_full_size():
+    """The 1.89e8-point Boltzmann-shaped grid the benchmark streams (3 GB of f
+    and sigma in host memory): 300 sampled points and both sides of every
+    2^24-point chunk boundary against the oracle."""
+    spec = wl.boltzmann_shape()
+    _say(f"chunked {spec.name}: {spec.G} points")
+    f, s = _zmc().scan_chunked(spec)
+    assert np.all(np.isfinite(f)) and np.all(np.isfinite(s))
+    C = 1 << 24
+    edges = np.arange(C, spec.G, C)
+    idx = np.concatenate([edges - 1, edges, [0, spec.G - 1],
+                          np.random.default_rng(3).choice(spec.G, 300, replace=False)])
+    idx = np.unique(idx).astype(np.uint64)
+    f_ref, s_ref = zo.scan(spec, idx)
+    ii = idx.astype(np.int64)
+    _, _, msg = parity.check(f[ii], s[ii], f_ref, s_ref, spec.samples, "fp32", spec.name,
+                             small_n=True, volume=1.0)
+    _say(msg)
