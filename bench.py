@@ -8,7 +8,7 @@ lists and the output buffers are resident in HBM before the timed region.
 
 Prints ONE JSON line on stdout.  Extra fields: the FP64 path on the same
 workload, per-step latency percentiles, the roofline of the main kernel
-(VALU-bound; algorithmic lane-operations per sample stated in the design doc),
+(VALU-bound; algorithmic lane-operations per sample from valu_ops_per_sample),
 the CPU oracle timed on a bounded sample of the same workload (and of the
 other workloads), and the paper's own throughput figures as context.
 
@@ -414,7 +414,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the scan shards by "
-              "grid-point ranges across GPUs with no exchange, which this build does not run.",
+              "grid-point ranges across GPUs with no exchange, which this library does not run.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -52,7 +52,7 @@ typedef enum zmc_status {
   ZMC_E_NOMEM = 2,       /* device or host allocation failed, or a buffer
                             the call would size exceeds 2^56 bytes         */
   ZMC_E_DEVICE = 3,      /* a HIP call failed (no device, launch error)   */
-  ZMC_E_UNSUPPORTED = 4, /* valid request this build does not implement   */
+  ZMC_E_UNSUPPORTED = 4, /* valid request the library does not implement  */
   ZMC_E_BUSY = 5         /* resource limit reached; retry later           */
 } zmc_status;
 
