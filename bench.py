@@ -36,8 +36,10 @@ VALU_PEAK = 256 * 128 * 2.4e9
 
 # HBM bytes per dispatch of the main kernel on the default workload, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy (profiles/), keyed
-# by the library version they were taken with; null for any other build.
-TRAFFIC_BYTES = {"zmc 0.7 gfx950": 0.412e6 + 144.0e6}
+# by the library version they were taken with; null for any other build.  The
+# FP32 Gaussian kernels of 0.7 and 0.8 compile to the same code (0.8 changed
+# only the FP64 sine and cosine).
+TRAFFIC_BYTES = {"zmc 0.7 gfx950": 0.412e6 + 144.0e6, "zmc 0.8 gfx950": 0.412e6 + 144.0e6}
 
 
 def valu_ops_per_sample(family, N):

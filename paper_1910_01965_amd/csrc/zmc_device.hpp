@@ -250,44 +250,40 @@ __device__ __forceinline__ float cos_turns(float r) {
   return __builtin_amdgcn_cosf(r - __builtin_rintf(r));
 }
 
-// FP64: sin(2 pi r + q pi/2) for a phase r in revolutions.  t = r - rint(r)
-// and u = t - rint(4t)/4 in [-1/8, 1/8] are exact (Sterbenz), x = 2 pi u lies
-// in [-pi/4, pi/4], and the octant picks sin x or cos x with its sign.  The
-// two Taylor polynomials (sine through x^17, cosine through x^16, Horner in
-// x^2, coefficients (-1)^k / n!) truncate below 3e-18; measured on the MI355X
-// against 80-bit sin(2 pi r): max error 1.5e-16 for |r| <= 64, where the
-// library's sin(2 pi r) reaches 4e-14, at 1.85x its throughput.
-__device__ __forceinline__ double sin_turns_q(double r, int shift) {
-  const double t = r - __builtin_rint(r);
-  const double qd = __builtin_rint(4.0 * t);
-  const double u = __builtin_fma(-0.25, qd, t);
-  const double x = u * 6.283185307179586476925286766559;
+// FP64 sine and cosine of a phase r in revolutions.  t = r - rint(r) lies in
+// [-1/2, 1/2] exactly.  Both reduce to sin(2 pi v) with v in [-1/4, 1/4]:
+//   sin: v = t for |t| <= 1/4, else v = copysign(1/2, t) - t (sin(pi - a) =
+//        sin a; exact, since 1/4 <= |t| <= 1/2);
+//   cos: v = 1/4 - |t| (cos a = sin(pi/2 - a); exact for |t| >= 1/8, else
+//        one rounding of at most 2^-55 revolutions).
+// x = 2 pi v lies in [-pi/2, pi/2], where the Taylor polynomial of sin
+// through x^21 (Horner in x^2, coefficients (-1)^k / (2k+1)!) truncates below
+// 1.3e-18.  One polynomial serves both functions, with no octant selection.
+__device__ __forceinline__ double sin_2pi_quarter(double v) {
+  const double x = v * 6.283185307179586476925286766559;
   const double x2 = x * x;
-  double ps = 2.8114572543455206e-15;       // 1/17!, then Horner down to -1/3!
-  ps = __builtin_fma(ps, x2, -7.647163731819816e-13);
-  ps = __builtin_fma(ps, x2, 1.6059043836821613e-10);
-  ps = __builtin_fma(ps, x2, -2.505210838544172e-08);
-  ps = __builtin_fma(ps, x2, 2.7557319223985893e-06);
-  ps = __builtin_fma(ps, x2, -0.0001984126984126984);
-  ps = __builtin_fma(ps, x2, 0.008333333333333333);
-  ps = __builtin_fma(ps, x2, -0.16666666666666666);
-  ps = __builtin_fma(ps * x2, x, x);        // sin x
-  double pc = 4.779477332387385e-14;         // 1/16!, then Horner down to 1
-  pc = __builtin_fma(pc, x2, -1.1470745597729725e-11);
-  pc = __builtin_fma(pc, x2, 2.08767569878681e-09);
-  pc = __builtin_fma(pc, x2, -2.755731922398589e-07);
-  pc = __builtin_fma(pc, x2, 2.48015873015873e-05);
-  pc = __builtin_fma(pc, x2, -0.001388888888888889);
-  pc = __builtin_fma(pc, x2, 0.041666666666666664);
-  pc = __builtin_fma(pc, x2, -0.5);
-  pc = __builtin_fma(pc, x2, 1.0);          // cos x
-  const int q = ((int)qd + shift) & 3;
-  const double v = (q & 1) ? pc : ps;
-  return (q & 2) ? -v : v;
+  double p = 1.9572941063391263e-20;       // 1/21!, then Horner down to -1/3!
+  p = __builtin_fma(p, x2, -8.22063524662433e-18);
+  p = __builtin_fma(p, x2, 2.8114572543455206e-15);
+  p = __builtin_fma(p, x2, -7.647163731819816e-13);
+  p = __builtin_fma(p, x2, 1.6059043836821613e-10);
+  p = __builtin_fma(p, x2, -2.505210838544172e-08);
+  p = __builtin_fma(p, x2, 2.7557319223985893e-06);
+  p = __builtin_fma(p, x2, -0.0001984126984126984);
+  p = __builtin_fma(p, x2, 0.008333333333333333);
+  p = __builtin_fma(p, x2, -0.16666666666666666);
+  return __builtin_fma(p * x2, x, x);
 }
 
-__device__ __forceinline__ double sin_turns(double r) { return sin_turns_q(r, 0); }
-__device__ __forceinline__ double cos_turns(double r) { return sin_turns_q(r, 1); }
+__device__ __forceinline__ double sin_turns(double r) {
+  const double t = r - __builtin_rint(r);
+  return sin_2pi_quarter(__builtin_fabs(t) > 0.25 ? __builtin_copysign(0.5, t) - t : t);
+}
+
+__device__ __forceinline__ double cos_turns(double r) {
+  const double t = r - __builtin_rint(r);
+  return sin_2pi_quarter(0.25 - __builtin_fabs(t));
+}
 
 // Parameter x_l of grid point g (C order: stride_l = prod_{j>l} L_j).
 __device__ __forceinline__ double param_x(const ScanParams& p, uint64_t g, int l) {
