@@ -187,6 +187,21 @@ def test_cosexp_full_grid_subsample(precision):
     _say(msg)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["point_major", "sample_major"])
+def test_eq2_large_phases(precision, mode):
+    """The paper's Eq. (2) integrand at its Table 1 extent (M = N = 4, x_l in
+    0..99, y in [0,10]^4): phases up to 436 rad, about 69 revolutions, so the
+    FP64 sine's reduction and fold run far from the origin on both branches."""
+    axis = np.array([0.0, 17.0, 38.0, 59.0, 80.0, 99.0])
+    spec = wl.ScanSpec("sin_sum", [axis] * 4, np.zeros(4), np.full(4, 10.0), 4099, 21, precision)
+    _say(f"eq2 large phases {precision} {mode} G={spec.G}")
+    f, s = _run(spec, mode=mode)
+    f_ref, s_ref = zo.scan(spec)
+    _, _, msg = parity.check(f, s, f_ref, s_ref, spec.samples, precision, f"eq2 {mode}")
+    _say(msg)
+
+
 # --------------------------------------------- decomposition, edge cases ----
 DECOMPOSITIONS = [
     dict(mode="point_major", splits=1), dict(mode="point_major", splits=3),
