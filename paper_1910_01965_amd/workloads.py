@@ -17,6 +17,8 @@ COSEXP are the two further benchmark integrands):
                   2..8, samples in {2^10..2^18}, family uniform, seeds 0..511
   boltzmann_shape 30^3 x 10^3 x 7 = 1.89e8 points, SIN_SUM over the seven
                   parameters, y in [0,1]^5, 1024 samples, seed 5 (out-of-core)
+  grid_1e10       10000 x 1000 x 1000 = 1e10 points, SIN_SUM, y in [0,1]^2,
+                  16 samples, seed 11 (160 GB of results, streamed in ranges)
 """
 from dataclasses import dataclass, field
 from typing import List
@@ -106,6 +108,15 @@ def boltzmann_shape(samples=1024, seed=5, precision="fp32"):
     axes = [np.linspace(0.0, 1.0, 30)] * 3 + [np.linspace(0.0, 0.5, 10)] * 3 + [np.arange(7.0)]
     return ScanSpec("sin_sum", axes, np.zeros(5), np.ones(5), samples, seed, precision,
                     name=f"boltzmann_shape_30^3x10^3x7_N5_n{samples}")
+
+
+def grid_1e10(samples=16, seed=11, precision="fp32"):
+    """A 10^10-point grid (10000 x 1000 x 1000 parameter values), the upper end
+    of the out-of-core scale: 160 GB of f and sigma, more than the device
+    holds, streamed to the host in ranges.  SIN_SUM over a 2-dimensional box."""
+    axes = [np.linspace(0.0, 1.0, 10000), np.linspace(0.0, 1.0, 1000), np.linspace(0.0, 1.0, 1000)]
+    return ScanSpec("sin_sum", axes, np.zeros(2), np.ones(2), samples, seed, precision,
+                    name=f"grid_10000x1000x1000_N2_n{samples}")
 
 
 def cosexp_subsample(G=10**8, k=10**4, seed=42):

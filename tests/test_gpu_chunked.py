@@ -173,3 +173,32 @@ def test_boltzmann_shaped_grid_at_full_size():
     _, _, msg = parity.check(f[ii], s[ii], f_ref, s_ref, spec.samples, "fp32", spec.name,
                              small_n=True, volume=1.0)
     _say(msg)
+
+
+def test_grid_of_1e10_points_by_ranges():
+    """A 10^10-point grid (160 GB of f and sigma) streamed in twenty ranges of
+    5e8 points through the same two host arrays, as a caller without 160 GB
+    of host memory would run it.  Each range: finite outputs, and its first
+    and last points and four sampled ones against the oracle (most of the
+    grid lies past 2^32, on the general counter path)."""
+    zmc = _zmc()
+    spec = wl.grid_1e10()
+    step = 500_000_000
+    f = np.empty(step)
+    s = np.empty(step)
+    rng = np.random.default_rng(12)
+    idx_all, f_all, s_all = [], [], []
+    for g0 in range(0, spec.G, step):
+        g1 = min(spec.G, g0 + step)
+        _say(f"grid 1e10: range [{g0}, {g1})")
+        zmc.scan_range(spec, g0, g1, 0, f[: g1 - g0], s[: g1 - g0])
+        assert np.all(np.isfinite(f[: g1 - g0])) and np.all(np.isfinite(s[: g1 - g0]))
+        local = np.concatenate([[0, g1 - g0 - 1], rng.integers(0, g1 - g0, 4)])
+        idx_all.append(g0 + local)
+        f_all.append(f[local].copy())
+        s_all.append(s[local].copy())
+    idx = np.concatenate(idx_all).astype(np.uint64)
+    f_ref, s_ref = zo.scan(spec, idx)
+    _, _, msg = parity.check(np.concatenate(f_all), np.concatenate(s_all), f_ref, s_ref,
+                             spec.samples, "fp32", spec.name, small_n=True, volume=1.0)
+    _say(msg)
