@@ -154,7 +154,8 @@ def batched_run(reps=1):
             "grid_pts_per_s": sum(sp.G for sp in specs) / t_batch}
 
 
-def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=32, compare_plain=False):
+def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=32, compare_plain=False,
+                admission="fifo"):
     """Poisson arrivals of scans shaped like the 512-scan batch (family,
     N, grid size, samples drawn by default_rng(seed); request i has Philox
     seed i) into the continuous-batching server; latency = completion -
@@ -169,7 +170,7 @@ def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=32, compare_p
     n_req = len(t_arr)
     specs = [sp.with_(seed=i) for i, sp in enumerate(wl.batched_512(count=n_req, seed=seed))]
     total = sum(sp.G * sp.samples for sp in specs)
-    srv = zmc.Server(hbm_budget_bytes=budget, max_slots=max_slots)
+    srv = zmc.Server(hbm_budget_bytes=budget, max_slots=max_slots, admission=admission)
     tickets = []
     t0 = time.perf_counter()
     for ta, sp in zip(t_arr, specs):
@@ -193,7 +194,7 @@ def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=32, compare_p
            "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                          "mean": float(lat.mean()), "max": float(lat.max())},
            "slices": stats["slices"], "bytes_peak": stats["bytes_peak"],
-           "budget_bytes": budget, "max_slots": max_slots}
+           "budget_bytes": budget, "max_slots": max_slots, "admission": admission}
     if compare_plain:
         outs = [(torch.empty(sp.G, dtype=torch.float64, device="cuda"),
                  torch.empty(sp.G, dtype=torch.float64, device="cuda")) for sp in specs]
@@ -534,12 +535,18 @@ def main():
         over = serving_run(200.0, args.serve_seconds, compare_plain=True)
         log(f"serving overload: {over['value']:.4g} samples/s, p50 {over['latency_s']['p50']:.3f} s, "
             f"p99 {over['latency_s']['p99']:.3f} s")
+        log(f"serving: 200 req/s for {args.serve_seconds} s, shortest first")
+        short = serving_run(200.0, args.serve_seconds, admission="shortest")
+        short["ratio_vs_plain"] = short["value"] / over["plain_back_to_back"]
+        log(f"serving overload, shortest first: {short['value']:.4g} samples/s, "
+            f"p50 {short['latency_s']['p50']:.3f} s, p99 {short['latency_s']['p99']:.3f} s")
         cap = out["batched"]["value"] if "batched" in out else over["plain_back_to_back"]
         mean_req = over["samples"] / max(1, over["requests"])
         steady_rate = 0.7 * cap / mean_req
         log(f"serving steady: {steady_rate:.1f} req/s for {2 * args.serve_seconds} s")
         steady = serving_run(steady_rate, 2 * args.serve_seconds, seed=8)
-        out["serving"] = {"overload_200_per_s": over, "steady_0p7_capacity": steady,
+        out["serving"] = {"overload_200_per_s": over, "overload_200_per_s_shortest_first": short,
+                          "steady_0p7_capacity": steady,
                           "what": "Poisson arrivals of 512-batch-shaped scans, 64 GiB budget, "
                                   "32 slots; latency = completion - submission"}
         out["latency_ms"]["serving_p50"] = steady["latency_s"]["p50"] * 1e3

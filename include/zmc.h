@@ -362,7 +362,23 @@ typedef struct zmc_server_opts {
   uint64_t slice_samples;      /* samples per slice, shared equally among
                                   the admitted requests, the rest oldest
                                   first (0 = 4e9, a few ms of device time)    */
+  int32_t admission;           /* zmc_admission: order of admission from the
+                                  queue (0 = arrival order)                  */
+  int32_t max_wait_ms;         /* ZMC_ADMIT_SHORTEST only: a request queued
+                                  longer than this is admitted before any
+                                  shorter one, oldest first (0 = no bound)    */
 } zmc_server_opts;
+
+/* Admission order.  Arrival order (FIFO) gives every request the same queueing
+ * delay.  Shortest first admits the queued request with the least estimated
+ * device work (G * samples * N) whenever a slot and budget are free: under
+ * overload most requests are small and finish within milliseconds, while the
+ * largest ones wait; max_wait_ms bounds that wait.  Results do not depend on
+ * the order (each request's f and sigma are bitwise its alone result). */
+typedef enum zmc_admission {
+  ZMC_ADMIT_FIFO = 0,
+  ZMC_ADMIT_SHORTEST = 1
+} zmc_admission;
 
 typedef struct zmc_server_stats {
   uint64_t submitted, admitted, completed, failed;

@@ -47,6 +47,7 @@ struct Request {
   uint64_t tile_samples = 1;  // samples per tile, averaged over the request's tiles
   uint64_t staged_doubles = 0;
   uint64_t footprint = 0;
+  double work = 0.0;          // estimated device work G * samples * N (admission order)
   zmc::UserKernels user;      // family ZMC_USER: kernels built for this shape
   unsigned user_blocks = 0;   // resident blocks of the user batch kernel
   void* dmem = nullptr;
@@ -290,6 +291,30 @@ void retire(zmc_server* s, Slice& sl) {
                   s->active.end());
 }
 
+// Queued requests in admission order: arrival order, or for shortest-first
+// ascending estimated work, equal work in arrival order.
+void enqueue_pending(zmc_server* s, const ReqPtr& r) {
+  if (s->opts.admission != ZMC_ADMIT_SHORTEST) {
+    s->pending.push_back(r);
+    return;
+  }
+  const auto at = std::upper_bound(s->pending.begin(), s->pending.end(), r,
+                                   [](const ReqPtr& a, const ReqPtr& b) { return a->work < b->work; });
+  s->pending.insert(at, r);
+}
+
+// Index in `pending` of the request to admit next: the front, unless a
+// shortest-first queue holds requests past max_wait_ms; then the oldest.
+size_t next_pending(const zmc_server* s) {
+  if (s->opts.admission != ZMC_ADMIT_SHORTEST || s->opts.max_wait_ms <= 0) return 0;
+  size_t oldest = 0;
+  for (size_t i = 1; i < s->pending.size(); ++i)
+    if (s->pending[i]->ticket < s->pending[oldest]->ticket) oldest = i;
+  const double waited =
+      std::chrono::duration<double>(Clock::now() - s->pending[oldest]->t_submit).count();
+  return waited * 1e3 > (double)s->opts.max_wait_ms ? oldest : 0;
+}
+
 void fail_all(zmc_server* s, zmc_status st) {
   for (Slice& sl : s->inflight)
     for (const ReqPtr& r : sl.finishing)
@@ -310,7 +335,7 @@ void run(zmc_server* s) {
     {
       std::lock_guard<std::mutex> lk(s->mu);
       while (!s->incoming.empty()) {
-        s->pending.push_back(s->incoming.front());
+        enqueue_pending(s, s->incoming.front());
         s->incoming.pop_front();
       }
       stopping = s->stop;
@@ -338,14 +363,15 @@ void run(zmc_server* s) {
     const int si = (int)(s->slice_count % kStreams);
     bool admitted = false;
     while (!s->pending.empty() && !s->free_slots.empty()) {
-      ReqPtr r = s->pending.front();
+      const size_t j = next_pending(s);
+      ReqPtr r = s->pending[j];
       if (r->footprint > s->opts.hbm_budget_bytes) {
-        s->pending.pop_front();
+        s->pending.erase(s->pending.begin() + (std::ptrdiff_t)j);
         finish(s, r, ZMC_E_NOMEM);
         continue;
       }
       if (s->bytes_in_use + r->footprint > s->opts.hbm_budget_bytes) break;
-      s->pending.pop_front();
+      s->pending.erase(s->pending.begin() + (std::ptrdiff_t)j);
       if (r->desc.family == ZMC_USER) {
         // built (first use of this shape) and loaded on the server's device
         const zmc_status us = zmc::user_kernels(r->desc.integrand, r->desc.precision, r->desc.N,
@@ -441,6 +467,11 @@ zmc_status zmc_server_create(const zmc_server_opts* opts, zmc_server** out) {
   if (o.max_slots > 65536 || o.max_inflight > 16) {
     delete s;
     return fail(ZMC_E_INVALID, "max_slots <= 65536 and max_inflight <= 16 required");
+  }
+  if ((o.admission != ZMC_ADMIT_FIFO && o.admission != ZMC_ADMIT_SHORTEST) || o.max_wait_ms < 0) {
+    delete s;
+    return fail(ZMC_E_INVALID, "admission must be ZMC_ADMIT_FIFO or ZMC_ADMIT_SHORTEST and "
+                "max_wait_ms >= 0");
   }
   s->ring = o.max_inflight + 1;
   hipError_t e = hipGetDevice(&s->device);
@@ -539,6 +570,7 @@ zmc_status zmc_server_submit(zmc_server* s, const zmc_scan_desc* desc, const dou
   r->tile_samples = (uint64_t)std::max(
       1.0, (double)G * (double)desc->samples / (double)std::max<uint64_t>(1, r->total_tiles));
   r->footprint = align_up(8 * r->staged_doubles) + r->plan.workspace_bytes;
+  r->work = (double)G * (double)r->desc.samples * (double)r->desc.N;
   r->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lk(s->mu);

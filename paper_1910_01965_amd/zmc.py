@@ -86,7 +86,10 @@ class BatchInfo(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
                 ("slice_tiles", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
-                ("cu_count", ctypes.c_int32), ("slice_samples", ctypes.c_uint64)]
+                ("cu_count", ctypes.c_int32), ("slice_samples", ctypes.c_uint64),
+                ("admission", ctypes.c_int32), ("max_wait_ms", ctypes.c_int32)]
+
+ADMISSION = {"fifo": 0, "shortest": 1}
 
 
 class ServerStats(ctypes.Structure):
@@ -519,9 +522,9 @@ class Server:
     alive until the request completes (the Server keeps a reference)."""
 
     def __init__(self, hbm_budget_bytes=0, max_slots=0, slice_tiles=0, max_inflight=0, cu_count=0,
-                 slice_samples=0):
+                 slice_samples=0, admission="fifo", max_wait_ms=0):
         o = ServerOpts(int(hbm_budget_bytes), int(max_slots), int(slice_tiles), int(max_inflight),
-                       int(cu_count), int(slice_samples))
+                       int(cu_count), int(slice_samples), ADMISSION[admission], int(max_wait_ms))
         h = ctypes.c_void_p()
         _check(load().zmc_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -304,3 +304,13 @@ def test_c_program_uses_the_abi_without_python():
     r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "passed (host-only part)" in r.stdout
+
+
+def test_server_rejects_bad_admission_options(lib):
+    # checked before any device call, so this runs without a GPU
+    out = ctypes.c_void_p()
+    for admission, max_wait in ((2, 0), (-1, 0), (1, -5)):
+        o = zmc.ServerOpts(0, 0, 0, 0, 0, 0, admission, max_wait)
+        assert lib.zmc_server_create(ctypes.byref(o), ctypes.byref(out)) == 1
+        assert b"admission" in lib.zmc_last_error()
+        assert not out.value

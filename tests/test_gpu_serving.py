@@ -178,3 +178,50 @@ def test_one_slot_serves_in_arrival_order():
     assert stats["submitted"] == stats["admitted"] == stats["completed"] == len(specs)
     assert stats["failed"] == 0
     srv.close()
+
+
+def _admission_order(admission, max_wait_ms):
+    """One slot; a long request is admitted and holds it while eight more of
+    distinct work are queued in an order that is not their size order.
+    Returns (work, completion time) of the eight in submission order, the
+    completion time being the host's submission time plus the latency the
+    server reports.  Every result still equals its alone run bit for bit."""
+    zmc = _zmc()
+    srv = zmc.Server(max_slots=1, admission=admission, max_wait_ms=max_wait_ms)
+    blocker = wl.gauss_2p(points_per_axis=1000, samples=1 << 16)
+    sizes = [7, 2, 5, 1, 8, 3, 6, 4]
+    specs = [wl.ScanSpec("gauss", [np.linspace(0.1, 10, 128 * k)] * 2, np.zeros(3), np.ones(3),
+                         1 << 16, 500 + k, "fp32") for k in sizes]
+    srv.submit(blocker)
+    t_end = time.perf_counter() + 10.0
+    while srv.stats()["admitted"] < 1 and time.perf_counter() < t_end:
+        time.sleep(0.0005)
+    assert srv.stats()["admitted"] == 1, "the long request was not admitted"
+    tickets, t_sub = [], []
+    for sp in specs:
+        tickets.append(srv.submit(sp))
+        t_sub.append(time.perf_counter())
+    done = [ts + srv.wait(t)[1] for ts, t in zip(t_sub, tickets)]
+    for sp, t in list(zip(specs, tickets))[::3]:
+        f, s = srv.outputs(t)
+        fa, sa = _alone(sp)
+        assert np.array_equal(f.cpu().numpy(), fa) and np.array_equal(s.cpu().numpy(), sa)
+    srv.close()
+    return [(sp.G * sp.samples * sp.N, c) for sp, c in zip(specs, done)]
+
+
+def test_shortest_first_admission():
+    """Shortest first: once the long request frees the slot, the queued ones
+    complete in ascending work.  With a 1 ms wait bound, below the long
+    request's run time, every queued request is overdue when the slot frees,
+    and the oldest-first rule restores arrival order."""
+    pairs = _admission_order("shortest", 0)
+    t0 = min(c for _, c in pairs)
+    _say(f"shortest first: {[(w, round(c - t0, 4)) for w, c in pairs]}")
+    by_work = [c for _, c in sorted(pairs)]
+    assert all(b > a for a, b in zip(by_work, by_work[1:]))
+    pairs = _admission_order("shortest", 1)
+    t0 = min(c for _, c in pairs)
+    _say(f"shortest first, 1 ms bound: {[round(c - t0, 4) for _, c in pairs]}")
+    arrival = [c for _, c in pairs]
+    assert all(b > a for a, b in zip(arrival, arrival[1:]))
