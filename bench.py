@@ -236,6 +236,26 @@ def cpu_baseline(spec, points, seed=0):
             "full_grid_one_core_s_extrapolated": full_s}
 
 
+def cpu_baseline_threads(spec, points, seed=0):
+    """The same oracle on the same seeded points, spread over the host's
+    cores: one oracle call per slice of points from a pool of threads (the
+    oracle's C entry point releases the interpreter lock and keeps no shared
+    state; its arithmetic is unchanged)."""
+    import concurrent.futures as cfut
+    from oracle import oracle as zo
+    idx = np.sort(np.random.default_rng(seed).choice(spec.G, points, replace=False)).astype(np.uint64)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    parts = np.array_split(idx, 8 * threads)
+    sp = spec.with_(precision="fp64")
+    t0 = time.perf_counter()
+    with cfut.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda part: zo.scan(sp, part), parts))
+    dt = time.perf_counter() - t0
+    return {"value": points * spec.samples / dt, "unit": "samples/s", "cores": threads,
+            "kind": "oracle", "seconds": dt,
+            "sample": f"the same {points} points on {threads} threads"}
+
+
 def cpu_baseline_others(seed=0):
     """The oracle on one host core for the other workloads: the whole
     1000-point plain FP64 scan, the 1e4-point subsample of the 1e8-point
@@ -554,6 +574,7 @@ def main():
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_points} points")
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_points)
+        out["cpu_baseline"]["all_host_cores"] = cpu_baseline_threads(spec, args.cpu_points)
         log("cpu baseline: oracle on the other workloads")
         out["cpu_baseline"]["other_workloads"] = cpu_baseline_others()
     else:
