@@ -6,9 +6,11 @@
 // admitted requests (each request cut into the same tiles a batch would use)
 // and runs them in one persistent kernel per precision; requests whose last
 // tile is in the slice get their split merge in the same slice and complete
-// when its event does.  Admission is FIFO, limited by the HBM budget for the
-// requests' own device state (staged lists and split partials) and by the
-// number of slots in the device table of scan descriptors.
+// when its event does.  Admission takes the queue in arrival order, or
+// shortest estimated work first (optionally with a bound on how long a
+// request may be passed over), limited by the HBM budget for the requests'
+// own device state (staged lists and split partials) and by the number of
+// slots in the device table of scan descriptors.
 #include <string.h>
 
 #include <algorithm>
