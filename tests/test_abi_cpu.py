@@ -314,3 +314,22 @@ def test_server_rejects_bad_admission_options(lib):
         assert lib.zmc_server_create(ctypes.byref(o), ctypes.byref(out)) == 1
         assert b"admission" in lib.zmc_last_error()
         assert not out.value
+
+
+def test_tune_table_source():
+    # the tile table next to libzmc.so by default; ZMC_TUNE_TABLE overrides it,
+    # and a missing file falls back to the built-in shapes (host only)
+    import subprocess
+    import sys
+    code = "from paper_1910_01965_amd import zmc\nprint(zmc.tune_source())\n"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = {k: v for k, v in os.environ.items() if k != "ZMC_TUNE_TABLE"}
+    runs = {}
+    for name, extra in (("default", {}), ("missing", {"ZMC_TUNE_TABLE": "/nonexistent/t.txt"})):
+        r = subprocess.run([sys.executable, "-c", code], cwd=root, env=dict(env, **extra),
+                           capture_output=True, text=True, timeout=120)
+        assert r.returncode == 0, r.stderr
+        runs[name] = r.stdout.strip()
+    expected = os.path.join(os.path.dirname(zmc.LIB_PATH), "tune_table.txt")
+    assert os.path.realpath(runs["default"]) == os.path.realpath(expected)
+    assert runs["missing"] == "built-in defaults"
