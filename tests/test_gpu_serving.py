@@ -90,13 +90,16 @@ def test_mix_equals_alone_and_oracle():
     srv.close()
 
 
-def test_budget_admission_and_oversized_request():
+@pytest.mark.parametrize("admission,max_wait_ms", [("fifo", 0), ("shortest", 0), ("shortest", 1)])
+def test_budget_admission_and_oversized_request(admission, max_wait_ms):
     zmc = _zmc()
     specs = _requests(10, seed=8)
     plans = [zmc.batch_plan([sp]) for sp in specs]
     need = [p["workspace_bytes"] for p in plans]
     budget = int(max(need) * 1.5) + (1 << 20)
-    srv = zmc.Server(hbm_budget_bytes=budget, max_slots=4, slice_tiles=256)
+    _say(f"budget admission {admission} max_wait_ms={max_wait_ms}")
+    srv = zmc.Server(hbm_budget_bytes=budget, max_slots=4, slice_tiles=256, admission=admission,
+                     max_wait_ms=max_wait_ms)
     tickets = [srv.submit(sp) for sp in specs]
     for t in tickets:
         st, _ = srv.wait(t)
@@ -107,10 +110,12 @@ def test_budget_admission_and_oversized_request():
     # a request whose own state exceeds the budget fails, the server carries on
     big = wl.gauss_2p(points_per_axis=1000, samples=1 << 16)
     t_big = srv.submit(big)
-    t_ok = srv.submit(specs[0])
+    t_ok = [srv.submit(sp) for sp in specs[:3]]
     st_big, _ = srv.wait(t_big)
-    st_ok, _ = srv.wait(t_ok)
-    assert st_big == 2 and st_ok == 0
+    assert st_big == 2 and all(srv.wait(t)[0] == 0 for t in t_ok)
+    f, s = srv.outputs(t_ok[1])
+    fa, sa = _alone(specs[1])
+    assert np.array_equal(f.cpu().numpy(), fa) and np.array_equal(s.cpu().numpy(), sa)
     srv.close()
 
 
