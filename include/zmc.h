@@ -391,7 +391,9 @@ typedef struct zmc_server_stats {
   uint64_t bytes_peak;
 } zmc_server_stats;
 
-/* Starts the scheduler thread on the current device.  submit, poll, wait
+/* Starts the scheduler thread on the current device (opts may be NULL for
+ * all defaults; max_slots > 65536, max_inflight > 16, an unknown admission
+ * or a negative max_wait_ms give ZMC_E_INVALID).  submit, poll, wait
  * and get_stats may be called from any number of threads at once; destroy
  * must not overlap any other call on the same server, and the handle is
  * invalid once it has returned. */
