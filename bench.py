@@ -194,7 +194,9 @@ def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=32, compare_p
            "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                          "mean": float(lat.mean()), "max": float(lat.max())},
            "slices": stats["slices"], "bytes_peak": stats["bytes_peak"],
-           "budget_bytes": budget, "max_slots": max_slots, "admission": admission}
+           "budget_bytes": budget, "max_slots": max_slots, "admission": admission,
+           "server_reported": {k: stats[k] for k in ("latency_p50_s", "latency_p99_s",
+                                                     "latency_max_s", "samples_per_s")}}
     if compare_plain:
         outs = [(torch.empty(sp.G, dtype=torch.float64, device="cuda"),
                  torch.empty(sp.G, dtype=torch.float64, device="cuda")) for sp in specs]

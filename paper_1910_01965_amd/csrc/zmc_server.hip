@@ -99,6 +99,9 @@ struct zmc_server {
   uint64_t next_ticket = 1;
   bool stop = false;
   zmc_server_stats stats{};
+  std::vector<double> latencies;   // completed requests, for the percentiles
+  Clock::time_point t_first_submit, t_last_done;
+  bool any_submitted = false;
   // scheduler-thread state
   std::deque<ReqPtr> pending, active;
   std::deque<Slice> inflight;
@@ -133,6 +136,8 @@ void finish(zmc_server* s, const ReqPtr& r, zmc_status st) {
   if (st == ZMC_OK) {
     s->stats.completed++;
     s->stats.samples_completed += r->G * r->desc.samples;
+    s->latencies.push_back(r->latency);
+    s->t_last_done = Clock::now();
   } else {
     s->stats.failed++;
   }
@@ -579,6 +584,10 @@ zmc_status zmc_server_submit(zmc_server* s, const zmc_scan_desc* desc, const dou
     if (s->stop) return fail(ZMC_E_BUSY, "server is shutting down");
     r->ticket = s->next_ticket++;
     s->tickets[r->ticket] = r;
+    if (!s->any_submitted) {
+      s->any_submitted = true;
+      s->t_first_submit = r->t_submit;
+    }
     s->incoming.push_back(r);
     s->stats.submitted++;
   }
@@ -613,8 +622,30 @@ zmc_status zmc_server_wait(zmc_server* s, uint64_t ticket, zmc_status* result, d
 
 zmc_status zmc_server_get_stats(zmc_server* s, zmc_server_stats* stats) {
   if (s == nullptr || stats == nullptr) return fail(ZMC_E_INVALID, "NULL argument");
-  std::lock_guard<std::mutex> lk(s->mu);
-  *stats = s->stats;
+  std::vector<double> v;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    *stats = s->stats;
+    v = s->latencies;
+    const double span =
+        std::chrono::duration<double>(s->t_last_done - s->t_first_submit).count();
+    stats->samples_per_s =
+        (!v.empty() && span > 0.0) ? (double)s->stats.samples_completed / span : 0.0;
+  }
+  stats->latency_p50_s = stats->latency_p99_s = stats->latency_max_s = 0.0;
+  if (!v.empty()) {
+    std::sort(v.begin(), v.end());
+    // linear interpolation between order statistics at q (n - 1)
+    const auto pct = [&v](double q) {
+      const double pos = q * (double)(v.size() - 1);
+      const size_t i = (size_t)pos;
+      const double frac = pos - (double)i;
+      return i + 1 < v.size() ? v[i] + frac * (v[i + 1] - v[i]) : v[i];
+    };
+    stats->latency_p50_s = pct(0.50);
+    stats->latency_p99_s = pct(0.99);
+    stats->latency_max_s = v.back();
+  }
   return ok();
 }
 

@@ -95,7 +95,9 @@ ADMISSION = {"fifo": 0, "shortest": 1}
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in (
         "submitted", "admitted", "completed", "failed", "pending", "active", "samples_completed",
-        "slices", "tiles", "bytes_in_use", "bytes_peak")]
+        "slices", "tiles", "bytes_in_use", "bytes_peak")] + [
+        (k, ctypes.c_double) for k in ("latency_p50_s", "latency_p99_s", "latency_max_s",
+                                       "samples_per_s")]
 
 
 _lib = None

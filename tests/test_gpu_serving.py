@@ -230,3 +230,26 @@ def test_shortest_first_admission():
     _say(f"shortest first, 1 ms bound: {[round(c - t0, 4) for _, c in pairs]}")
     arrival = [c for _, c in pairs]
     assert all(b > a for a, b in zip(arrival, arrival[1:]))
+
+
+def test_server_reports_latency_percentiles():
+    """The server's own p50 / p99 / max latency equal those of the latencies
+    it returned per request (same interpolation as numpy's default), and its
+    throughput is the completed samples over the span from first submission
+    to last completion."""
+    zmc = _zmc()
+    specs = _requests(24, seed=13, max_samples=1 << 12)
+    srv = zmc.Server(max_slots=8)
+    assert srv.stats()["latency_p50_s"] == 0.0 and srv.stats()["samples_per_s"] == 0.0
+    tickets = [srv.submit(sp) for sp in specs]
+    lat = np.array([srv.wait(t)[1] for t in tickets])
+    st = srv.stats()
+    srv.close()
+    _say(f"server-reported p50 {st['latency_p50_s']:.6f} p99 {st['latency_p99_s']:.6f} "
+         f"max {st['latency_max_s']:.6f} s, {st['samples_per_s']:.4g} samples/s")
+    assert np.isclose(st["latency_p50_s"], np.percentile(lat, 50), rtol=1e-12, atol=0)
+    assert np.isclose(st["latency_p99_s"], np.percentile(lat, 99), rtol=1e-12, atol=0)
+    assert st["latency_max_s"] == lat.max()
+    total = sum(sp.G * sp.samples for sp in specs)
+    assert st["samples_completed"] == total
+    assert 0.0 < st["samples_per_s"] <= total / lat.max()
