@@ -118,12 +118,21 @@ static void device_checks(const double* gauss_vals, const int64_t* gauss_len) {
   uint64_t t[NS];
   for (int i = 0; i < NS; ++i)
     expect(zmc_server_submit(srv, &sc[i], NULL, d_f2[i], d_s2[i], &t[i]) == ZMC_OK, "zmc_server_submit");
+  double lat_max = 0.0;
   for (int i = 0; i < NS; ++i) {
     zmc_status st = ZMC_E_DEVICE;
     double lat = -1.0;
     expect(zmc_server_wait(srv, t[i], &st, &lat) == ZMC_OK && st == ZMC_OK && lat >= 0.0,
            "zmc_server_wait: done");
+    if (lat > lat_max) lat_max = lat;
   }
+  zmc_server_stats ss;
+  memset(&ss, 0, sizeof(ss));
+  expect(zmc_server_get_stats(srv, &ss) == ZMC_OK && ss.completed == (uint64_t)NS &&
+             ss.latency_max_s == lat_max && ss.latency_p50_s > 0.0 &&
+             ss.latency_p50_s <= ss.latency_p99_s && ss.latency_p99_s <= ss.latency_max_s &&
+             ss.samples_per_s > 0.0,
+         "zmc_server_get_stats: counts, latency percentiles, throughput");
   expect(zmc_server_destroy(srv) == ZMC_OK, "zmc_server_destroy");
   int same = 1;
   for (int i = 0; i < NS; ++i) {
