@@ -389,10 +389,10 @@ typedef struct zmc_server_stats {
   uint64_t tiles;              /* tiles launched                             */
   uint64_t bytes_in_use;       /* device state held by admitted requests     */
   uint64_t bytes_peak;
-  /* Over the requests completed so far (0 before the first): latency
-   * (completion - submission, seconds) at the 50th and 99th percentiles
-   * (linear interpolation between order statistics) and its maximum, and
-   * samples_completed / (last completion - first submission). */
+  /* Over the most recent 65536 completed requests (0 before the first):
+   * latency (completion - submission, seconds) at the 50th and 99th
+   * percentiles (linear interpolation between order statistics) and its
+   * maximum; and samples_completed / (last completion - first submission). */
   double latency_p50_s, latency_p99_s, latency_max_s;
   double samples_per_s;
 } zmc_server_stats;

@@ -69,6 +69,9 @@ struct Slice {
 };
 
 constexpr int kStreams = 2;
+// The latency percentiles cover the most recent completions only, so that a
+// long-running server's memory and get_stats cost stay bounded.
+constexpr size_t kLatencyWindow = 65536;
 
 }  // namespace
 
@@ -99,7 +102,8 @@ struct zmc_server {
   uint64_t next_ticket = 1;
   bool stop = false;
   zmc_server_stats stats{};
-  std::vector<double> latencies;   // completed requests, for the percentiles
+  std::vector<double> latencies;   // latest kLatencyWindow completions (a ring)
+  uint64_t latency_count = 0;      // completions recorded in the ring so far
   Clock::time_point t_first_submit, t_last_done;
   bool any_submitted = false;
   // scheduler-thread state
@@ -136,7 +140,11 @@ void finish(zmc_server* s, const ReqPtr& r, zmc_status st) {
   if (st == ZMC_OK) {
     s->stats.completed++;
     s->stats.samples_completed += r->G * r->desc.samples;
-    s->latencies.push_back(r->latency);
+    if (s->latencies.size() < kLatencyWindow)
+      s->latencies.push_back(r->latency);
+    else
+      s->latencies[s->latency_count % kLatencyWindow] = r->latency;
+    s->latency_count++;
     s->t_last_done = Clock::now();
   } else {
     s->stats.failed++;
@@ -578,10 +586,10 @@ zmc_status zmc_server_submit(zmc_server* s, const zmc_scan_desc* desc, const dou
       1.0, (double)G * (double)desc->samples / (double)std::max<uint64_t>(1, r->total_tiles));
   r->footprint = align_up(8 * r->staged_doubles) + r->plan.workspace_bytes;
   r->work = (double)G * (double)r->desc.samples * (double)r->desc.N;
-  r->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return fail(ZMC_E_BUSY, "server is shutting down");
+    r->t_submit = Clock::now();  // in ticket order: the oldest request has the lowest ticket
     r->ticket = s->next_ticket++;
     s->tickets[r->ticket] = r;
     if (!s->any_submitted) {
