@@ -395,6 +395,8 @@ typedef struct zmc_server_stats {
    * maximum; and samples_completed / (last completion - first submission). */
   double latency_p50_s, latency_p99_s, latency_max_s;
   double samples_per_s;
+  uint64_t tickets;            /* requests still tracked: submitted and not yet
+                                  released with zmc_server_release           */
 } zmc_server_stats;
 
 /* Starts the scheduler thread on the current device (opts may be NULL for
@@ -406,9 +408,12 @@ typedef struct zmc_server_stats {
 zmc_status zmc_server_create(const zmc_server_opts* opts, zmc_server** out);
 
 /* Queues one scan; never waits for the GPU.  The descriptor and its host
- * arrays are copied.  d_axis_vals may be NULL (the server stages
- * desc->axis_vals); d_f and d_sigma (G doubles each) must stay valid until
- * the request completes.  *ticket identifies the request. */
+ * arrays are copied (and dropped once the request finishes).  d_axis_vals
+ * may be NULL (the server stages desc->axis_vals); d_f and d_sigma (G
+ * doubles each) must stay valid until the request completes, and no work on
+ * another stream may still be using them when submit is called (the server
+ * writes them from its own streams).  *ticket identifies the request until
+ * zmc_server_release. */
 zmc_status zmc_server_submit(zmc_server* server, const zmc_scan_desc* desc,
                              const double* d_axis_vals, double* d_f, double* d_sigma,
                              uint64_t* ticket);
@@ -421,6 +426,13 @@ zmc_status zmc_server_poll(zmc_server* server, uint64_t ticket, int32_t* done,
 /* Blocks until the request has finished. */
 zmc_status zmc_server_wait(zmc_server* server, uint64_t ticket, zmc_status* result,
                            double* latency_s);
+
+/* Forgets a finished request: its ticket becomes unknown to poll, wait and
+ * release (ZMC_E_INVALID), and the server drops what it still held for it
+ * (status and latency).  ZMC_E_BUSY if the request has not finished.  A
+ * server keeps every unreleased ticket until zmc_server_destroy, so a
+ * long-running caller releases each request once it has read its result. */
+zmc_status zmc_server_release(zmc_server* server, uint64_t ticket);
 
 zmc_status zmc_server_get_stats(zmc_server* server, zmc_server_stats* stats);
 

@@ -52,6 +52,19 @@ void log(int level, const char* fmt, ...) {
   fprintf(stderr, "[zmc] %s\n", line);
 }
 
+// Every plan (make_plan for single scans, plan_tiles for batches and the
+// server) passes here before any ScanParams is filled from it: the pieces
+// [sp * gps, min((sp + 1) * gps, groups)) must cover the groups exactly once
+// with none empty, since the device loops assume j0 <= the piece's last group.
+zmc_status check_pieces(uint64_t groups, uint64_t gps, uint64_t splits) {
+  if (groups < 1 || gps < 1 || splits < 1 || splits > 0x7FFFFFFFull ||
+      (splits - 1) * gps >= groups || splits * gps < groups)
+    return fail(ZMC_E_INVALID, "plan: %llu pieces of %llu groups do not cover %llu groups "
+                "exactly once", (unsigned long long)splits, (unsigned long long)gps,
+                (unsigned long long)groups);
+  return ZMC_OK;
+}
+
 }  // namespace zmc
 
 namespace {
@@ -207,6 +220,8 @@ zmc_status make_plan(const zmc_scan_desc* d, uint64_t G, const zmc_launch_opts* 
   if (splits > groups) splits = groups;
   const uint64_t gps = cdiv(groups, splits);
   splits = cdiv(groups, gps);  // no empty piece
+  zmc_status pst = zmc::check_pieces(groups, gps, splits);
+  if (pst != ZMC_OK) return pst;
   if (splits > 1 && G > kMaxBytes / (16 * splits))
     return fail(ZMC_E_NOMEM, "split partials of %llu points x %llu pieces exceed %llu bytes",
                 (unsigned long long)G, (unsigned long long)splits, (unsigned long long)kMaxBytes);

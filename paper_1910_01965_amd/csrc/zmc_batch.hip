@@ -46,6 +46,8 @@ zmc_status plan_tiles(const zmc_scan_desc* d, uint64_t G, int64_t pm_groups_over
   if (splits > 0x7FFFFFFFull) return fail(ZMC_E_UNSUPPORTED, "too many sample pieces");
   const uint64_t gps = (groups + splits - 1) / splits;
   splits = (groups + gps - 1) / gps;
+  const zmc_status pst = check_pieces(groups, gps, splits);
+  if (pst != ZMC_OK) return pst;
   pl->splits = (int)splits;
   pl->groups = groups;
   pl->gps = gps;

@@ -37,6 +37,7 @@ void log(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 zmc_status fail(zmc_status st, const char* fmt, ...);
 zmc_status ok();
 zmc_status validate_desc(const zmc_scan_desc* d, uint64_t* G);
+zmc_status check_pieces(uint64_t groups, uint64_t gps, uint64_t splits);
 zmc_status cu_count(int* cu);
 void fill_scan_params(const zmc_scan_desc* d, uint64_t G, const Plan& pl, const double* d_axis,
                       double* d_f, double* d_sigma, ScanParams* p);

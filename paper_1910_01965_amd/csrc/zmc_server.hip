@@ -134,6 +134,19 @@ void finish(zmc_server* s, const ReqPtr& r, zmc_status st) {
   r->latency = std::chrono::duration<double>(Clock::now() - r->t_submit).count();
   zmc::log(2, "server: request %llu done, status %d, %.6f s after submit",
            (unsigned long long)r->ticket, (int)st, r->latency);
+  if (st == ZMC_OK) {
+    // every copy and kernel of the request has completed, so the host copies
+    // of its descriptor are not read again: a finished request keeps only its
+    // status and latency until zmc_server_release (after a failure they stay
+    // until then, since a copy from them may not have run)
+    std::vector<int64_t>().swap(r->axis_len);
+    std::vector<double>().swap(r->axis_vals);
+    std::vector<double>().swap(r->lo);
+    std::vector<double>().swap(r->hi);
+    std::vector<double>().swap(r->params);
+    r->desc.axis_len = nullptr;
+    r->desc.axis_vals = r->desc.lo = r->desc.hi = r->desc.params = nullptr;
+  }
   std::lock_guard<std::mutex> lk(s->mu);
   r->status = st;
   r->done = true;
@@ -628,12 +641,24 @@ zmc_status zmc_server_wait(zmc_server* s, uint64_t ticket, zmc_status* result, d
   return ok();
 }
 
+zmc_status zmc_server_release(zmc_server* s, uint64_t ticket) {
+  if (s == nullptr) return fail(ZMC_E_INVALID, "NULL server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return fail(ZMC_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  if (!it->second->done)
+    return fail(ZMC_E_BUSY, "request %llu has not finished", (unsigned long long)ticket);
+  s->tickets.erase(it);  // a thread still in zmc_server_wait holds its own reference
+  return ok();
+}
+
 zmc_status zmc_server_get_stats(zmc_server* s, zmc_server_stats* stats) {
   if (s == nullptr || stats == nullptr) return fail(ZMC_E_INVALID, "NULL argument");
   std::vector<double> v;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     *stats = s->stats;
+    stats->tickets = (uint64_t)s->tickets.size();
     v = s->latencies;
     const double span =
         std::chrono::duration<double>(s->t_last_done - s->t_first_submit).count();

@@ -26,7 +26,8 @@ EXPORTS = ("zmc_last_error", "zmc_version", "zmc_validate", "zmc_plan", "zmc_sca
            "zmc_batch_default_opts", "zmc_batch_plan", "zmc_batch_create", "zmc_batch_launch",
            "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch", "zmc_tune_source",
            "zmc_server_create", "zmc_server_submit", "zmc_server_poll", "zmc_server_wait",
-           "zmc_server_get_stats", "zmc_server_destroy", "zmc_integrand_create",
+           "zmc_server_get_stats", "zmc_server_release", "zmc_server_destroy",
+           "zmc_integrand_create",
            "zmc_integrand_log", "zmc_integrand_destroy", "zmc_scan_chunked", "zmc_scan_range",
            "zmc_debug_valu_probe")
 
@@ -97,7 +98,7 @@ class ServerStats(ctypes.Structure):
         "submitted", "admitted", "completed", "failed", "pending", "active", "samples_completed",
         "slices", "tiles", "bytes_in_use", "bytes_peak")] + [
         (k, ctypes.c_double) for k in ("latency_p50_s", "latency_p99_s", "latency_max_s",
-                                       "samples_per_s")]
+                                       "samples_per_s")] + [("tickets", ctypes.c_uint64)]
 
 
 _lib = None
@@ -148,6 +149,7 @@ def load():
         lib.zmc_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_double)]
         lib.zmc_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        lib.zmc_server_release.argtypes = [vp, ctypes.c_uint64]
         lib.zmc_server_destroy.argtypes = [vp]
         lib.zmc_integrand_create.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
         lib.zmc_integrand_log.argtypes = [vp]
@@ -160,7 +162,8 @@ def load():
                      "zmc_batch_plan", "zmc_batch_create", "zmc_batch_launch",
                      "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch",
                      "zmc_server_create", "zmc_server_submit", "zmc_server_poll",
-                     "zmc_server_wait", "zmc_server_get_stats", "zmc_server_destroy"):
+                     "zmc_server_wait", "zmc_server_get_stats", "zmc_server_release",
+                     "zmc_server_destroy"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -299,12 +302,14 @@ def scan_device(spec, d_axis, f, sigma, stream=None, mode=None, block=None, spli
 
 
 def scan(spec, mode=None, block=None, splits=None, stream=None):
-    """(f, sigma) float64 device tensors for every grid point of `spec`."""
+    """(f, sigma) float64 device tensors for every grid point of `spec`,
+    allocated on and computed on `stream` (default: the current stream)."""
     import torch
     G = validate(spec)
-    d_axis = axis_tensor(spec)
-    f = torch.empty(G, dtype=torch.float64, device="cuda")
-    s = torch.empty(G, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+        d_axis = axis_tensor(spec)
+        f = torch.empty(G, dtype=torch.float64, device="cuda")
+        s = torch.empty(G, dtype=torch.float64, device="cuda")
     scan_device(spec, d_axis, f, s, stream=stream, mode=mode, block=block, splits=splits)
     return f, s
 
@@ -520,8 +525,16 @@ def tune_source():
 # ---------------------------------------------------------------- serving ---
 class Server:
     """Continuous-batching request loop (zmc_server_*).  `submit` returns a
-    ticket immediately; outputs are float64 device tensors that must stay
-    alive until the request completes (the Server keeps a reference)."""
+    ticket immediately.  Outputs are float64 device tensors that the Server
+    keeps alive until they are handed over (`outputs`) or the request is
+    released (`release`); `outputs` also releases the request, so a
+    long-running caller holds memory only for requests it has not collected.
+
+    Outputs the Server allocates come from a stream of its own on which no
+    work is ever queued, so torch's caching allocator never hands it a block
+    that pending work on another stream still uses; at hand-over they are
+    marked as used on the current stream.  Outputs passed in by the caller
+    must not be in use by pending work on other streams when submitted."""
 
     def __init__(self, hbm_budget_bytes=0, max_slots=0, slice_tiles=0, max_inflight=0, cu_count=0,
                  slice_samples=0, admission="fifo", max_wait_ms=0):
@@ -531,14 +544,19 @@ class Server:
         _check(load().zmc_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h
         self._keep = {}
+        self._alloc_stream = None
 
     def submit(self, spec, f=None, sigma=None, axis=None):
         import torch
         G = validate(spec)
-        if f is None:
-            f = torch.empty(G, dtype=torch.float64, device="cuda")
-        if sigma is None:
-            sigma = torch.empty(G, dtype=torch.float64, device="cuda")
+        if f is None or sigma is None:
+            if self._alloc_stream is None:
+                self._alloc_stream = torch.cuda.Stream()
+            with torch.cuda.stream(self._alloc_stream):
+                if f is None:
+                    f = torch.empty(G, dtype=torch.float64, device="cuda")
+                if sigma is None:
+                    sigma = torch.empty(G, dtype=torch.float64, device="cuda")
         d = Desc(spec)
         t = ctypes.c_uint64()
         _check(load().zmc_server_submit(self._h, d.ref,
@@ -549,8 +567,26 @@ class Server:
         return t.value
 
     def outputs(self, ticket):
+        """(f, sigma) of a finished request, handed over to the caller: the
+        Server forgets the request (its ticket becomes unknown).  After
+        close() every request has finished and its outputs can still be
+        collected."""
+        import torch
         f, s, _ = self._keep[ticket]
+        if getattr(self, "_h", None):
+            self.release(ticket)
+        else:
+            del self._keep[ticket]
+        cur = torch.cuda.current_stream()
+        f.record_stream(cur)
+        s.record_stream(cur)
         return f, s
+
+    def release(self, ticket):
+        """Forget a finished request and drop the Server's references to its
+        outputs (zmc_server_release; raises while it is still running)."""
+        _check(load().zmc_server_release(self._h, int(ticket)))
+        self._keep.pop(ticket, None)
 
     def poll(self, ticket):
         """(done, status, latency_s)."""
@@ -574,6 +610,8 @@ class Server:
         return {k: getattr(st, k) for k, _ in ServerStats._fields_}
 
     def close(self):
+        """Finish every submitted request and free the server; outputs not yet
+        collected stay available through `outputs`."""
         if getattr(self, "_h", None):
             _check(load().zmc_server_destroy(self._h))
             self._h = None

@@ -133,6 +133,18 @@ static void device_checks(const double* gauss_vals, const int64_t* gauss_len) {
              ss.latency_p50_s <= ss.latency_p99_s && ss.latency_p99_s <= ss.latency_max_s &&
              ss.samples_per_s > 0.0,
          "zmc_server_get_stats: counts, latency percentiles, throughput");
+  expect(ss.tickets == (uint64_t)NS, "zmc_server_get_stats: every ticket still tracked");
+  for (int i = 0; i < NS; ++i)
+    expect(zmc_server_release(srv, t[i]) == ZMC_OK, "zmc_server_release of a finished request");
+  {
+    int32_t done = 0;
+    expect(zmc_server_poll(srv, t[0], &done, NULL, NULL) == ZMC_E_INVALID &&
+               zmc_server_release(srv, t[0]) == ZMC_E_INVALID,
+           "a released ticket is unknown");
+    memset(&ss, 0, sizeof(ss));
+    expect(zmc_server_get_stats(srv, &ss) == ZMC_OK && ss.tickets == 0 && ss.completed == (uint64_t)NS,
+           "zmc_server_get_stats: no ticket tracked after release");
+  }
   expect(zmc_server_destroy(srv) == ZMC_OK, "zmc_server_destroy");
   int same = 1;
   for (int i = 0; i < NS; ++i) {

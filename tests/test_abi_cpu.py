@@ -96,7 +96,9 @@ def _covers(p):
                                   wl.gauss_2p(points_per_axis=9, samples=4097)])
 def test_plans_cover_all_work(lib, spec):
     for mode in ("auto", "point_major", "sample_major"):
-        for splits in (None, 1, 3, 1000):
+        # explicit splits up to and past the group count (ragged sample
+        # counts included): the planner never leaves a piece empty
+        for splits in (None, 1, 3, 1000, 1024, 1025, 4097, 65535):
             p = zmc.plan(spec, mode=mode, splits=splits, cu_count=256)
             _covers(p)
             assert p["grid_points"] == spec.G

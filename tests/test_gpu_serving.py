@@ -253,3 +253,56 @@ def test_server_reports_latency_percentiles():
     total = sum(sp.G * sp.samples for sp in specs)
     assert st["samples_completed"] == total
     assert 0.0 < st["samples_per_s"] <= total / lat.max()
+
+
+def test_released_requests_hold_no_memory():
+    """3000 small requests, each collected (outputs) or released once it has
+    finished: the server tracks no ticket afterwards, the binding keeps no
+    output, and device memory returns to where it started; a request still
+    running cannot be released."""
+    import torch
+    zmc = _zmc()
+    base = wl.ScanSpec("gauss", [np.linspace(0.5, 2.0, 16), np.linspace(0.5, 2.0, 16)],
+                       np.zeros(3), np.ones(3), 64, 0, "fp32", name="gauss_16x16_n64")
+    blocker = wl.gauss_2p(precision="fp32", samples=1 << 16)
+    srv = zmc.Server(max_slots=1)
+    t_block = srv.submit(blocker)
+    t_next = srv.submit(base)
+    with pytest.raises(zmc.ZmcError) as err:
+        srv.release(t_next)  # waits behind the blocker for its only slot
+    assert err.value.status == 5
+    srv.wait(t_block)
+    srv.wait(t_next)
+    srv.release(t_block)
+    srv.release(t_next)
+    srv.close()
+    torch.cuda.synchronize()
+    mem0 = torch.cuda.memory_allocated()
+    srv = zmc.Server(max_slots=64)
+    live, peak = [], 0
+    f_ref = s_ref = None
+    for i in range(3000):
+        live.append((i, srv.submit(base.with_(seed=i % 50))))
+        if len(live) > 32:
+            j, t = live.pop(0)
+            assert srv.wait(t)[0] == 0
+            if j % 50 == 7 and f_ref is None:
+                f, s = srv.outputs(t)
+                f_ref, s_ref = f.cpu().numpy(), s.cpu().numpy()
+            elif j % 50 == 7:
+                f, s = srv.outputs(t)
+                assert np.array_equal(f.cpu().numpy(), f_ref) and np.array_equal(s.cpu().numpy(), s_ref)
+            else:
+                srv.release(t)
+        peak = max(peak, torch.cuda.memory_allocated() - mem0)
+    for _, t in live:
+        assert srv.wait(t)[0] == 0
+        srv.release(t)
+    st = srv.stats()
+    assert st["completed"] == 3000 and st["tickets"] == 0 and not srv._keep
+    srv.close()
+    torch.cuda.synchronize()
+    _say(f"3000 released requests: peak {peak} B of outputs above the start, "
+         f"{torch.cuda.memory_allocated() - mem0} B at the end")
+    assert peak <= 34 * 2 * 16 * base.G * 2  # at most the live requests' f and sigma (+ cache rounding)
+    assert torch.cuda.memory_allocated() - mem0 <= 2 * 16 * base.G * 4
