@@ -200,6 +200,25 @@ zmc_status zmc_scan_device_ex(const zmc_scan_desc* desc, const double* d_axis_va
                               double* d_f, double* d_sigma,
                               const zmc_launch_opts* opts, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture that must record no memory nodes, tight serving loops, harnesses
+ * that forbid hipMalloc): zmc_scan_device with the same arguments, the same
+ * plan and the same kernels, so its f and sigma equal zmc_scan_device's bit
+ * for bit, but it calls no hipMalloc, hipFree or allocating routine.  The
+ * split partials of its plan (16 B per point and sample piece) live in a
+ * fixed device array of ZMC_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each device it runs on until the process ends; the first call on a device
+ * looks up that device's copy (make one call before capturing).  Plans
+ * whose partials exceed the array (e.g. 1e6 points x 9 pieces = 144 MB) give
+ * ZMC_E_NOMEM and launch nothing; ZMC_USER scans give ZMC_E_UNSUPPORTED
+ * (their kernels are built and loaded on first use).  Every call on a device
+ * shares its array and leaves its contents behind (nothing in it needs to
+ * start at zero): calls that overlap on one device race, so the caller
+ * orders them (one stream, or events).  Asynchronous on `stream`. */
+#define ZMC_NOALLOC_SCRATCH_BYTES ((uint64_t)128 << 20)
+zmc_status zmc_scan_device_noalloc(const zmc_scan_desc* desc, const double* d_axis_vals,
+                                   double* d_f, double* d_sigma, void* stream);
+
 /* Debug: words w0 .. w0+count-1 of grid point g's Philox stream, computed by
  * the device generator, into d_out (count uint32).  Asynchronous. */
 zmc_status zmc_debug_words(uint64_t seed, uint64_t g, uint64_t w0, int64_t count,

@@ -373,6 +373,84 @@ zmc_status zmc_scan_device(const zmc_scan_desc* desc, const double* d_axis_vals,
   return zmc_scan_device_ex(desc, d_axis_vals, d_f, d_sigma, nullptr, stream);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Scratch of zmc_scan_device_noalloc: the split partials of its plans live in
+// this fixed device array instead of stream-ordered allocations.  Each device
+// holds its own copy (reserved when the library's code is loaded there, kept
+// until the process ends), at its own address: host code uses the address
+// that hipGetSymbolAddress returns on that device, never the array's name,
+// which on the host is only a stand-in.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[ZMC_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The current device's copy of `scratch`, looked up once per device.
+zmc_status scratch_on_current_device(void** out) {
+  int dev = 0;
+  ZMC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(ZMC_E_UNSUPPORTED, "device %d: the allocation-free scan serves devices 0..%d", dev,
+                kMaxScratchDevices - 1);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      return fail(ZMC_E_DEVICE, "scratch of the allocation-free scan on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return ZMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+zmc_status zmc_scan_device_noalloc(const zmc_scan_desc* desc, const double* d_axis_vals,
+                                   double* d_f, double* d_sigma, void* stream) {
+  uint64_t G = 0;
+  zmc_status st = validate(desc, &G);
+  if (st != ZMC_OK) return st;
+  if (desc->family == ZMC_USER)
+    return fail(ZMC_E_UNSUPPORTED, "the allocation-free scan runs the compiled-in families only "
+                                   "(a user integrand's kernels are built and loaded on first use)");
+  if (desc->M > 0 && d_axis_vals == nullptr) return fail(ZMC_E_INVALID, "d_axis_vals is NULL with M > 0");
+  if (d_f == nullptr || d_sigma == nullptr) return fail(ZMC_E_INVALID, "d_f or d_sigma is NULL");
+  // set-up on the first call on a device: the address of its scratch
+  void* base = nullptr;
+  st = scratch_on_current_device(&base);
+  if (st != ZMC_OK) return st;
+  zmc::Plan pl;
+  st = make_plan(desc, G, nullptr, &pl);
+  if (st != ZMC_OK) return st;
+  if (pl.workspace_bytes > ZMC_NOALLOC_SCRATCH_BYTES)
+    return fail(ZMC_E_NOMEM,
+                "split partials of %llu points x %d pieces need %llu bytes, more than the %llu "
+                "bytes of the allocation-free scan's scratch (zmc_scan_device allocates them)",
+                (unsigned long long)G, pl.splits, (unsigned long long)pl.workspace_bytes,
+                (unsigned long long)ZMC_NOALLOC_SCRATCH_BYTES);
+  zmc::ScanParams p;
+  fill_params(desc, G, pl, d_axis_vals, d_f, d_sigma, &p);
+  if (pl.workspace_bytes > 0) {
+    // every (piece, point) slot is written by the main kernel before the
+    // merge pass reads it, so nothing needs clearing
+    p.part_mean = (double*)base;
+    p.part_m2 = p.part_mean + (uint64_t)pl.splits * G;
+  }
+  const hipError_t e = zmc::launch_scan(p, pl, desc->precision, (hipStream_t)stream, nullptr, nullptr);
+  if (e != hipSuccess) return fail(ZMC_E_DEVICE, "scan launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
 zmc_status zmc_scan(const zmc_scan_desc* desc, double* f, double* sigma) {
   uint64_t G = 0;
   zmc_status st = validate(desc, &G);

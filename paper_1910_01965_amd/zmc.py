@@ -22,7 +22,8 @@ STATUS = {0: "ZMC_OK", 1: "ZMC_E_INVALID", 2: "ZMC_E_NOMEM", 3: "ZMC_E_DEVICE",
           4: "ZMC_E_UNSUPPORTED", 5: "ZMC_E_BUSY"}
 
 EXPORTS = ("zmc_last_error", "zmc_version", "zmc_validate", "zmc_plan", "zmc_scan",
-           "zmc_scan_device", "zmc_scan_device_ex", "zmc_debug_words", "zmc_debug_values",
+           "zmc_scan_device", "zmc_scan_device_ex", "zmc_scan_device_noalloc", "zmc_debug_words",
+           "zmc_debug_values",
            "zmc_batch_default_opts", "zmc_batch_plan", "zmc_batch_create", "zmc_batch_launch",
            "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch", "zmc_tune_source",
            "zmc_server_create", "zmc_server_submit", "zmc_server_poll", "zmc_server_wait",
@@ -124,6 +125,7 @@ def load():
         lib.zmc_scan_range.argtypes = [descp, ctypes.c_uint64, ctypes.c_uint64, vp, vp, ctypes.c_uint64]
         lib.zmc_scan_device.argtypes = [descp, vp, vp, vp, vp]
         lib.zmc_scan_device_ex.argtypes = [descp, vp, vp, vp, ctypes.POINTER(LaunchOpts), vp]
+        lib.zmc_scan_device_noalloc.argtypes = [descp, vp, vp, vp, vp]
         lib.zmc_debug_words.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                         ctypes.c_int64, vp, vp]
         lib.zmc_debug_values.argtypes = [descp, vp, ctypes.c_uint64, ctypes.c_uint64,
@@ -158,7 +160,7 @@ def load():
         for name in ("zmc_integrand_create", "zmc_integrand_destroy", "zmc_scan_chunked",
                      "zmc_scan_range",
                      "zmc_validate", "zmc_plan", "zmc_scan", "zmc_scan_device",
-                     "zmc_scan_device_ex", "zmc_debug_words", "zmc_debug_values",
+                     "zmc_scan_device_ex", "zmc_scan_device_noalloc", "zmc_debug_words", "zmc_debug_values",
                      "zmc_batch_plan", "zmc_batch_create", "zmc_batch_launch",
                      "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch",
                      "zmc_server_create", "zmc_server_submit", "zmc_server_poll",
@@ -299,6 +301,20 @@ def scan_device(spec, d_axis, f, sigma, stream=None, mode=None, block=None, spli
     _check(load().zmc_scan_device_ex(d.ref, ctypes.c_void_p(d_axis.data_ptr()),
                                      ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(sigma.data_ptr()),
                                      ctypes.byref(o) if o else None, _stream_ptr(stream)))
+
+
+def scan_device_noalloc(spec, d_axis, f, sigma, stream=None):
+    """Enqueue the scan of `spec` through the allocation-free entry point:
+    the plan and results of scan_device, with the split partials in the
+    library's fixed per-device scratch (ZmcError with status 2 when they do
+    not fit it)."""
+    d = Desc(spec)
+    _check(load().zmc_scan_device_noalloc(d.ref, ctypes.c_void_p(d_axis.data_ptr()),
+                                          ctypes.c_void_p(f.data_ptr()),
+                                          ctypes.c_void_p(sigma.data_ptr()), _stream_ptr(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20  # ZMC_NOALLOC_SCRATCH_BYTES of include/zmc.h
 
 
 def scan(spec, mode=None, block=None, splits=None, stream=None):
