@@ -77,8 +77,7 @@ typedef enum zmc_precision {
                            FP64 merging across lanes, waves, blocks, splits  */
 } zmc_precision;
 
-/* One scan.  Limits: 0 <= M <= 16; 1 <= N <= 8 (N <= 16 is a valid
- * descriptor, N > 8 returns ZMC_E_UNSUPPORTED); every axis_len >= 1;
+/* One scan.  Limits: 0 <= M <= 16; 1 <= N <= 16; every axis_len >= 1;
  * G = prod axis_len <= 2^62; lo_k < hi_k, both finite; samples >= 2 and
  * samples * N <= 2^62; n_params = 0 for the five compiled-in families,
  * 0 <= n_params <= 16 for ZMC_USER. */
@@ -113,7 +112,8 @@ typedef enum zmc_mode {
 
 typedef struct zmc_launch_opts {
   int32_t mode;          /* zmc_mode                                          */
-  int32_t block;         /* threads per block: 64..1024 (point-major: ..256),
+  int32_t block;         /* threads per block: 64..1024 (point-major, and any
+                            scan with N > 8: ..256),
                             multiple of 64                                    */
   int32_t splits;        /* sample-range pieces per point (>= 1)              */
   int32_t cu_count;      /* planner only: compute units assumed (0 = device)  */
@@ -232,6 +232,26 @@ zmc_status zmc_debug_words(uint64_t seed, uint64_t g, uint64_t w0, int64_t count
  * A launch that fills the device should read as ~100 % issue-busy in the
  * counters used for the scan kernels.  Asynchronous on `stream`. */
 zmc_status zmc_debug_valu_probe(int32_t blocks, int64_t iters, float* d_out, void* stream);
+
+/* Diagnostics: instruction-rate loads (not part of the method), one per
+ * instruction form that the scan kernels issue.  `blocks` blocks of 256
+ * threads each run `iters` loop trips of 64 instructions of the form (eight
+ * dependent chains per lane, each step reading three of them) and write one
+ * 64-bit word per thread to d_out (blocks x 256 words, device memory).
+ * Timing a launch gives the form's issue rate in lane-instructions per
+ * second.  Asynchronous on `stream`; ZMC_E_INVALID for an unknown op. */
+typedef enum zmc_rate_op {
+  ZMC_RATE_XOR_B32 = 0,      /* v_xor_b32: two-operand integer               */
+  ZMC_RATE_ADD_F32 = 1,      /* v_add_f32: two-operand FP32                  */
+  ZMC_RATE_FMA_F32 = 2,      /* v_fma_f32: three-operand FP32                */
+  ZMC_RATE_MAD_U64_U32 = 3,  /* v_mad_u64_u32: Philox's 32x32->64 product    */
+  ZMC_RATE_BITOP3_B32 = 4,   /* v_bitop3_b32: Philox's three-way xor         */
+  ZMC_RATE_EXP_F32 = 5,      /* v_exp_f32: the FP32 exp2 unit                */
+  ZMC_RATE_SIN_F32 = 6,      /* v_sin_f32: the FP32 sine unit                */
+  ZMC_RATE_FMA_F64 = 7       /* v_fma_f64                                     */
+} zmc_rate_op;
+zmc_status zmc_debug_rate_probe(int32_t op, int32_t blocks, int64_t iters, uint64_t* d_out,
+                                void* stream);
 
 /* Debug: integrand values g(y_s; x_g) for samples s = s0 .. s0+count-1 of
  * grid point g, computed by the device sampler and integrand in the

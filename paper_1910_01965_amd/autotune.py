@@ -41,7 +41,8 @@ def _time_batch(zmc, specs, reps, **opts):
 
 def variant_specs(family, precision, N, max_samples):
     from . import workloads as wl
-    out = [s for s in wl.batched_512(precision=precision) if s.family == family and s.N == N]
+    pool = wl.batched_512(precision=precision) if N <= 8 else wl.batched_wide(precision=precision)
+    out = [s for s in pool if s.family == family and s.N == N]
     if not out:
         out = [wl.family_shape(family, N, 64, 1 << 14, 0, precision)]
     return [s.with_(samples=min(s.samples, max_samples)) for s in out]
@@ -89,6 +90,8 @@ def main(argv=None):
     ap.add_argument("--dims", default="2,3,4,5,6,7,8")
     ap.add_argument("--max-samples", type=int, default=1 << 15)
     ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--merge", action="store_true",
+                    help="keep the rows of the existing table for variants not tuned in this run")
     args = ap.parse_args(argv)
 
     import torch
@@ -111,6 +114,16 @@ def main(argv=None):
                 pm = tune_pm_groups(zmc, specs, args.reps, log)
                 pmin = tune_pm_min(zmc, family, precision, N, pm, args.reps, log)
                 rows.append((family, precision, N, pm, SM_GROUPS, pmin))
+    if args.merge and os.path.exists(args.out):
+        tuned = {(r[0], r[1], r[2]) for r in rows}
+        kept = []
+        with open(args.out) as fh:
+            for line in fh:
+                f = line.split("#", 1)[0].split()
+                if len(f) == 6 and (f[0], f[1], int(f[2])) not in tuned:
+                    kept.append((f[0], f[1], int(f[2]), int(f[3]), int(f[4]), int(f[5])))
+        rows = sorted(kept + rows, key=lambda r: (r[1] != "fp32", ("sin_sum", "gauss", "cosexp").index(r[0])
+                                                  if r[0] in ("sin_sum", "gauss", "cosexp") else 9, r[2]))
     props = torch.cuda.get_device_properties(0)
     with open(args.out + ".tmp", "w") as fh:
         fh.write("# zmc tile-shape table, written by paper_1910_01965_amd/autotune.py on "

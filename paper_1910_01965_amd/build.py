@@ -17,12 +17,14 @@ LIB = os.path.join(HERE, "libzmc.so")
 FAMILIES = ("SinSum", "Gauss", "CosExp", "Const", "Linear")
 REALS = ("float", "double")
 # (source, extra defines, object name): the family kernels build one
-# translation unit per (family, precision) so that they compile in parallel
+# translation unit per (family, precision, N = 1..8 or 9..16) so that they
+# compile in parallel
 SOURCES = ([("zmc_api.hip", (), "zmc_api"), ("zmc_batch.hip", (), "zmc_batch"),
             ("zmc_tune.hip", (), "zmc_tune"), ("zmc_kernels.hip", (), "zmc_kernels"),
             ("zmc_server.hip", (), "zmc_server"), ("zmc_rtc.hip", (), "zmc_rtc")]
-           + [("zmc_family.hip", (f"-DZMC_FAMILY={f}", f"-DZMC_REAL={r}"), f"zmc_{f}_{r}")
-              for f in FAMILIES for r in REALS]
+           + [("zmc_family.hip", (f"-DZMC_FAMILY={f}", f"-DZMC_REAL={r}", f"-DZMC_NLO={lo}"),
+               f"zmc_{f}_{r}_N{lo}")
+              for f in FAMILIES for r in REALS for lo in (1, 9)]
            + [("zmc_any.hip", (f"-DZMC_REAL={r}",), f"zmc_any_{r}") for r in REALS])
 ARCH = "gfx950"
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")

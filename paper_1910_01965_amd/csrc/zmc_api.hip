@@ -95,7 +95,8 @@ zmc_status validate(const zmc_scan_desc* d, uint64_t* G_out) {
     if (G > kMaxG / (uint64_t)L) return fail(ZMC_E_INVALID, "grid larger than 2^62 points");
     G *= (uint64_t)L;
   }
-  if (d->N < 1 || d->N > 16) return fail(ZMC_E_INVALID, "N = %d outside 1..16", d->N);
+  if (d->N < 1 || d->N > zmc::kMaxDims)
+    return fail(ZMC_E_INVALID, "N = %d outside 1..%d", d->N, zmc::kMaxDims);
   if (d->lo == nullptr || d->hi == nullptr) return fail(ZMC_E_INVALID, "lo or hi is NULL");
   for (int k = 0; k < d->N; ++k) {
     if (!isfinite(d->lo[k]) || !isfinite(d->hi[k]))
@@ -133,8 +134,6 @@ zmc_status validate(const zmc_scan_desc* d, uint64_t* G_out) {
   } else if (d->n_params != 0) {
     return fail(ZMC_E_INVALID, "n_params = %d; these families take none", d->n_params);
   }
-  if (d->N > zmc::kMaxDims)
-    return fail(ZMC_E_UNSUPPORTED, "N = %d > %d is not built", d->N, zmc::kMaxDims);
   if (G_out) *G_out = G;
   return ok();
 }
@@ -198,6 +197,8 @@ zmc_status make_plan(const zmc_scan_desc* d, uint64_t G, const zmc_launch_opts* 
     return fail(ZMC_E_INVALID, "block = %d: needs a multiple of 64 in 64..1024", block);
   if (mode == ZMC_MODE_POINT_MAJOR && block > 256)
     return fail(ZMC_E_INVALID, "point-major blocks hold at most 256 threads");
+  if (d->N > zmc::kAnyMaxDims && block > 256)
+    return fail(ZMC_E_INVALID, "blocks of scans with N > %d hold at most 256 threads", zmc::kAnyMaxDims);
   uint64_t splits = (o && o->splits > 0) ? (uint64_t)o->splits : 0;
   if (splits == 0) {
     if (mode == ZMC_MODE_POINT_MAJOR) {
@@ -499,6 +500,17 @@ zmc_status zmc_debug_valu_probe(int32_t blocks, int64_t iters, float* d_out, voi
   if (iters < 1) return fail(ZMC_E_INVALID, "iters = %lld < 1", (long long)iters);
   if (d_out == nullptr) return fail(ZMC_E_INVALID, "d_out is NULL");
   hipError_t e = zmc::launch_valu_probe(blocks, iters, d_out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(ZMC_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+zmc_status zmc_debug_rate_probe(int32_t op, int32_t blocks, int64_t iters, uint64_t* d_out,
+                                void* stream) {
+  if (op < ZMC_RATE_XOR_B32 || op > ZMC_RATE_FMA_F64) return fail(ZMC_E_INVALID, "unknown op %d", op);
+  if (blocks < 1 || blocks > (1 << 20)) return fail(ZMC_E_INVALID, "blocks = %d outside 1..2^20", blocks);
+  if (iters < 1) return fail(ZMC_E_INVALID, "iters = %lld < 1", (long long)iters);
+  if (d_out == nullptr) return fail(ZMC_E_INVALID, "d_out is NULL");
+  hipError_t e = zmc::launch_rate_probe(op, blocks, iters, d_out, (hipStream_t)stream);
   if (e != hipSuccess) return fail(ZMC_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
   return ok();
 }

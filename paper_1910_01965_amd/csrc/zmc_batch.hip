@@ -150,7 +150,7 @@ zmc_status plan_batch(const zmc_scan_desc* scans, int32_t n, const zmc_batch_opt
     if (scans[i].family == ZMC_USER)
       keys.push_back(VariantKey{scans[i].precision, ZMC_USER, scans[i].N, scans[i].integrand,
                                 scans[i].M});
-    else if (o && o->one_kernel)
+    else if (o && o->one_kernel && scans[i].N <= zmc::kAnyMaxDims)
       keys.push_back(VariantKey{scans[i].precision, -1, 0});
     else
       keys.push_back(VariantKey{scans[i].precision, scans[i].family, scans[i].N});

@@ -24,7 +24,8 @@ using __hip_internal::uint64_t;
 namespace zmc {
 
 constexpr int kMaxParams = 16;
-constexpr int kMaxDims = 8;
+constexpr int kMaxDims = 16;
+constexpr int kAnyMaxDims = 8;  // integration dimensions of the any-family batch kernel
 constexpr int kMaxUserParams = 16;  // constants passed to a user integrand
 
 // Everything a scan kernel needs, passed by value as the kernel argument.
@@ -505,14 +506,29 @@ template <class Fam, typename T, int N, class Gen>
 __device__ __forceinline__ void eval_group(const Fam& fam, uint64_t j, const Gen& gen, T v[4]) {
   T t[4 * N];
   const uint64_t b0 = j * (uint64_t)N;
+  if constexpr (N <= kAnyMaxDims) {
 #pragma unroll
-  for (int c = 0; c < N; ++c) {
-    const Words4 w = gen.block(b0 + c);
+    for (int c = 0; c < N; ++c) {
+      const Words4 w = gen.block(b0 + c);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) t[4 * c + i] = Unif<T>::t(w.r[i]);
+      for (int i = 0; i < 4; ++i) t[4 * c + i] = Unif<T>::t(w.r[i]);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = fam.value(t + s * N);
+  } else {
+    // many dimensions: sample s is evaluated right after the block that holds
+    // its last word (word sN + N - 1), so that only the variates of about one
+    // sample are live at a time; the values are the same
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      const Words4 w = gen.block(b0 + c);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) t[4 * c + i] = Unif<T>::t(w.r[i]);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if ((s * N + N - 1) / 4 == c) v[s] = fam.value(t + s * N);
+    }
   }
-#pragma unroll
-  for (int s = 0; s < 4; ++s) v[s] = fam.value(t + s * N);
 }
 
 // Runs body(f) with f = the family's reduced form (Fam::UnitForm) when the

@@ -71,6 +71,8 @@ hipError_t launch_debug_words(uint64_t seed, uint64_t g, uint64_t w0, int64_t co
                               uint32_t* out, hipStream_t stream);
 hipError_t launch_merge_splits(const ScanParams& p, hipStream_t stream);
 hipError_t launch_valu_probe(int32_t blocks, int64_t iters, float* out, hipStream_t stream);
+hipError_t launch_rate_probe(int32_t op, int32_t blocks, int64_t iters, uint64_t* out,
+                             hipStream_t stream);
 
 // Kernels of a user integrand for one (precision, N, M), built on first use.
 struct UserKernels {

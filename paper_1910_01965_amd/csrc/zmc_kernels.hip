@@ -63,24 +63,104 @@ __global__ __launch_bounds__(256) void k_valu_probe(int64_t iters, float* out) {
   out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
 }
 
+// Instruction-rate loads for the roofline's op mix: each lane runs eight
+// dependent chains of one instruction form, 64 instructions per loop trip
+// (loop control on the scalar unit), every step reading two or three chains
+// so that nothing folds.  The forms are those the scan kernels issue: two-operand
+// xor and add, three-operand FP32 fma, the 32x32->64 multiply-add and the
+// three-input xor of Philox, the FP32 exp2 and sine units, and FP64 fma.
+template <int Op> struct RateOp;
+// xor steps alternate with integer adds (both two-operand forms), since a
+// chain of xors alone is linear and the compiler folds it
+template <> struct RateOp<ZMC_RATE_XOR_B32> {
+  using V = uint32_t;
+  static __device__ V init(unsigned t, int i) { return 0x9E3779B9u * (t + 1u) + (V)i; }
+  static __device__ __forceinline__ V step(V a, V b, V, int u) { return (u & 1) ? a + b : a ^ b; }
+};
+template <> struct RateOp<ZMC_RATE_ADD_F32> {
+  using V = float;
+  static __device__ V init(unsigned t, int i) { return 1e-3f * (float)t + (float)i; }
+  static __device__ __forceinline__ V step(V a, V b, V, int) { return a + b; }
+};
+template <> struct RateOp<ZMC_RATE_FMA_F32> {
+  using V = float;
+  static __device__ V init(unsigned t, int i) { return 1.0f + 1e-6f * (float)t + 1e-3f * (float)i; }
+  static __device__ __forceinline__ V step(V a, V b, V c, int) { return __builtin_fmaf(a, b, c); }
+};
+template <> struct RateOp<ZMC_RATE_MAD_U64_U32> {
+  using V = uint64_t;
+  static __device__ V init(unsigned t, int i) { return 0xD2511F53ull * (t + 1u) + (V)i; }
+  static __device__ __forceinline__ V step(V a, V b, V c, int) {
+    return (uint64_t)(uint32_t)a * (uint32_t)b + c;
+  }
+};
+template <> struct RateOp<ZMC_RATE_BITOP3_B32> {
+  using V = uint32_t;
+  static __device__ V init(unsigned t, int i) { return 0xCD9E8D57u * (t + 1u) + (V)i; }
+  static __device__ __forceinline__ V step(V a, V b, V c, int) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+  }
+};
+template <> struct RateOp<ZMC_RATE_EXP_F32> {
+  using V = float;
+  static __device__ V init(unsigned t, int i) { return 1e-4f * (float)t + 0.1f * (float)i; }
+  static __device__ __forceinline__ V step(V a, V, V, int) { return __builtin_amdgcn_exp2f(-a); }
+};
+template <> struct RateOp<ZMC_RATE_SIN_F32> {
+  using V = float;
+  static __device__ V init(unsigned t, int i) { return 1e-4f * (float)t + 0.1f * (float)i; }
+  static __device__ __forceinline__ V step(V a, V, V, int) { return __builtin_amdgcn_sinf(a); }
+};
+template <> struct RateOp<ZMC_RATE_FMA_F64> {
+  using V = double;
+  static __device__ V init(unsigned t, int i) { return 1.0 + 1e-9 * (double)t + 1e-3 * (double)i; }
+  static __device__ __forceinline__ V step(V a, V b, V c, int) { return __builtin_fma(a, b, c); }
+};
+
+template <int Op>
+__global__ __launch_bounds__(256) void k_rate_probe(int64_t iters, uint64_t* out) {
+  using R = RateOp<Op>;
+  typename R::V x[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) x[i] = R::init(threadIdx.x, i);
+  for (int64_t it = 0; it != iters; ++it) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) x[i] = R::step(x[i], x[(i + 1) & 7], x[(i + 2) & 7], u);
+    }
+  }
+  uint64_t h = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    uint64_t bits = 0;
+    __builtin_memcpy(&bits, &x[i], sizeof(x[i]));
+    h ^= bits + (uint64_t)i;
+  }
+  out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = h;
+}
+
 namespace {
 
-template <typename T, class Fn>
+template <typename T, int Lo, class Fn>
 hipError_t by_family(int family, const Fn& fn) {
   switch (family) {
-    case ZMC_SIN_SUM: return fn(FamilyOps<SinSum, T>{});
-    case ZMC_GAUSS: return fn(FamilyOps<Gauss, T>{});
-    case ZMC_COSEXP: return fn(FamilyOps<CosExp, T>{});
-    case ZMC_CONST: return fn(FamilyOps<Const, T>{});
-    case ZMC_LINEAR: return fn(FamilyOps<Linear, T>{});
+    case ZMC_SIN_SUM: return fn(FamilyOps<SinSum, T, Lo>{});
+    case ZMC_GAUSS: return fn(FamilyOps<Gauss, T, Lo>{});
+    case ZMC_COSEXP: return fn(FamilyOps<CosExp, T, Lo>{});
+    case ZMC_CONST: return fn(FamilyOps<Const, T, Lo>{});
+    case ZMC_LINEAR: return fn(FamilyOps<Linear, T, Lo>{});
     default: return hipErrorInvalidValue;
   }
 }
 
+// N = 1..8 and 9..16 are built in separate translation units.
 template <class Fn>
-hipError_t by_precision(int precision, int family, const Fn& fn) {
-  if (precision == ZMC_FP64) return by_family<double>(family, fn);
-  return by_family<float>(family, fn);
+hipError_t by_precision(int precision, int family, int N, const Fn& fn) {
+  constexpr int Wide = 1 + kDimsPerUnit;
+  if (precision == ZMC_FP64)
+    return N < Wide ? by_family<double, 1>(family, fn) : by_family<double, Wide>(family, fn);
+  return N < Wide ? by_family<float, 1>(family, fn) : by_family<float, Wide>(family, fn);
 }
 
 }  // namespace
@@ -90,7 +170,7 @@ hipError_t launch_scan(const ScanParams& p, const Plan& plan, int precision, hip
   hipError_t e = hipSuccess;
   if (ev_begin != nullptr) e = hipEventRecord(ev_begin, stream);
   if (e == hipSuccess)
-    e = by_precision(precision, p.family, [&](auto ops) { return ops.main(p.N, p, plan, stream); });
+    e = by_precision(precision, p.family, p.N, [&](auto ops) { return ops.main(p.N, p, plan, stream); });
   if (e == hipSuccess && ev_end != nullptr) e = hipEventRecord(ev_end, stream);
   if (e != hipSuccess || p.splits == 1) return e;
   return launch_merge_splits(p, stream);
@@ -104,13 +184,13 @@ hipError_t launch_merge_splits(const ScanParams& p, hipStream_t stream) {
 }
 
 hipError_t batch_occupancy(int precision, int family, int N, int* blocks_per_cu) {
-  return by_precision(precision, family, [&](auto ops) { return ops.occupancy(N, blocks_per_cu); });
+  return by_precision(precision, family, N, [&](auto ops) { return ops.occupancy(N, blocks_per_cu); });
 }
 
 hipError_t launch_batch_variant(int precision, int family, int N, const ScanParams* scans,
                                 const Tile* tiles, uint32_t begin, uint32_t end,
                                 uint32_t* counter, unsigned blocks, hipStream_t stream) {
-  return by_precision(precision, family, [&](auto ops) {
+  return by_precision(precision, family, N, [&](auto ops) {
     return ops.batch(N, scans, tiles, begin, end, counter, blocks, stream);
   });
 }
@@ -158,8 +238,25 @@ hipError_t launch_valu_probe(int32_t blocks, int64_t iters, float* out, hipStrea
 hipError_t launch_debug_values(const ScanParams& p, int precision, uint64_t g, uint64_t s0,
                                int64_t count, double* out, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
-  return by_precision(precision, p.family,
+  return by_precision(precision, p.family, p.N,
                       [&](auto ops) { return ops.values(p.N, p, g, s0, count, out, stream); });
+}
+
+hipError_t launch_rate_probe(int32_t op, int32_t blocks, int64_t iters, uint64_t* out,
+                             hipStream_t stream) {
+  const dim3 grid((unsigned)blocks), block(256);
+  switch (op) {
+    case ZMC_RATE_XOR_B32: hipLaunchKernelGGL(k_rate_probe<ZMC_RATE_XOR_B32>, grid, block, 0, stream, iters, out); break;
+    case ZMC_RATE_ADD_F32: hipLaunchKernelGGL(k_rate_probe<ZMC_RATE_ADD_F32>, grid, block, 0, stream, iters, out); break;
+    case ZMC_RATE_FMA_F32: hipLaunchKernelGGL(k_rate_probe<ZMC_RATE_FMA_F32>, grid, block, 0, stream, iters, out); break;
+    case ZMC_RATE_MAD_U64_U32: hipLaunchKernelGGL(k_rate_probe<ZMC_RATE_MAD_U64_U32>, grid, block, 0, stream, iters, out); break;
+    case ZMC_RATE_BITOP3_B32: hipLaunchKernelGGL(k_rate_probe<ZMC_RATE_BITOP3_B32>, grid, block, 0, stream, iters, out); break;
+    case ZMC_RATE_EXP_F32: hipLaunchKernelGGL(k_rate_probe<ZMC_RATE_EXP_F32>, grid, block, 0, stream, iters, out); break;
+    case ZMC_RATE_SIN_F32: hipLaunchKernelGGL(k_rate_probe<ZMC_RATE_SIN_F32>, grid, block, 0, stream, iters, out); break;
+    case ZMC_RATE_FMA_F64: hipLaunchKernelGGL(k_rate_probe<ZMC_RATE_FMA_F64>, grid, block, 0, stream, iters, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace zmc

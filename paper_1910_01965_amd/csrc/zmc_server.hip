@@ -4,7 +4,9 @@
 // between them so that the next slice's blocks start while the previous
 // slice's last tiles finish.  Every slice takes tiles round-robin from all
 // admitted requests (each request cut into the same tiles a batch would use)
-// and runs them in one persistent kernel per precision; requests whose last
+// and runs them in one persistent kernel per precision (user integrands and
+// scans of more than eight dimensions in kernels of their own, one per
+// variant); requests whose last
 // tile is in the slice get their split merge in the same slice and complete
 // when its event does.  Admission takes the queue in arrival order, or
 // shortest estimated work first (optionally with a bound on how long a
@@ -51,7 +53,8 @@ struct Request {
   uint64_t footprint = 0;
   double work = 0.0;          // estimated device work G * samples * N (admission order)
   zmc::UserKernels user;      // family ZMC_USER: kernels built for this shape
-  unsigned user_blocks = 0;   // resident blocks of the user batch kernel
+  unsigned own_blocks = 0;    // resident blocks of the request's own batch kernel
+                              // (user integrands; compiled-in N > kAnyMaxDims)
   void* dmem = nullptr;
   int alloc_stream = 0;
   int slot = -1;
@@ -81,7 +84,7 @@ struct zmc_server {
   hipStream_t streams[kStreams] = {nullptr, nullptr};
   unsigned blocks32 = 1, blocks64 = 1;
   int cu = 1;
-  int counters_per_slot = 2;  // FP32 and FP64 any-family kernels, then user variants
+  int counters_per_slot = 2;  // FP32 and FP64 any-family kernels, then one per own-kernel variant (at most one per admitted request)
   int ring = 3;
   // device memory: slot table | tile ring | counter ring | merge ring
   void* dmem = nullptr;
@@ -192,6 +195,18 @@ hipError_t admit(zmc_server* s, const ReqPtr& r, int si) {
   return e;
 }
 
+// Requests whose tiles run in a batch kernel of their own rather than in the
+// any-family kernel of their precision, and whether two of them share it.
+bool own_kernel(const Request& r) {
+  return r.desc.family == ZMC_USER || r.desc.N > zmc::kAnyMaxDims;
+}
+
+bool same_variant(const Request& a, const Request& b) {
+  if (a.desc.family != b.desc.family || a.desc.precision != b.desc.precision || a.desc.N != b.desc.N)
+    return false;
+  return a.desc.family != ZMC_USER || (a.desc.integrand == b.desc.integrand && a.desc.M == b.desc.M);
+}
+
 // One slice on stream `si`: work round-robin over the admitted requests (an
 // equal share of the slice's samples each, then what is left in admission
 // order), FP32 tiles then FP64 tiles, one persistent kernel for each; then
@@ -226,34 +241,34 @@ hipError_t launch_slice(zmc_server* s, int si, Slice* out) {
     used += more;
     used_samples += more * r.tile_samples;
   }
-  // tile table: compiled-in FP32 tiles, FP64 tiles, then one group per user
-  // variant (integrand, precision, N, M)
+  // tile table: FP32 tiles and FP64 tiles of the any-family kernels, then one
+  // group per variant that runs in a kernel of its own: a user integrand
+  // (integrand, precision, N, M) or a compiled-in family with
+  // N > kAnyMaxDims (family, precision, N)
   uint32_t n32 = 0, n = 0;
   for (int pass = 0; pass < 2; ++pass) {
     const int prec = pass == 0 ? ZMC_FP32_MERGE64 : ZMC_FP64;
     for (auto& tk : take) {
       Request& r = *tk.first;
-      if (r.desc.precision != prec || r.desc.family == ZMC_USER) continue;
+      if (r.desc.precision != prec || own_kernel(r)) continue;
       for (uint64_t t = 0; t < tk.second; ++t) ht[n++] = tile_of(r, r.next_tile + t);
     }
     if (pass == 0) n32 = n;
   }
   const uint32_t n_builtin = n;
-  struct UserGroup {
+  struct VariantGroup {
     const Request* first;
     uint32_t begin, end;
   };
-  std::vector<UserGroup> groups;
+  std::vector<VariantGroup> groups;
   std::vector<bool> placed(take.size(), false);
   for (size_t a = 0; a < take.size(); ++a) {
     const Request& ra = *take[a].first;
-    if (ra.desc.family != ZMC_USER || placed[a]) continue;
-    UserGroup grp{&ra, n, n};
+    if (!own_kernel(ra) || placed[a]) continue;
+    VariantGroup grp{&ra, n, n};
     for (size_t b = a; b < take.size(); ++b) {
       Request& rb = *take[b].first;
-      if (placed[b] || rb.desc.family != ZMC_USER || rb.desc.integrand != ra.desc.integrand ||
-          rb.desc.precision != ra.desc.precision || rb.desc.N != ra.desc.N || rb.desc.M != ra.desc.M)
-        continue;
+      if (placed[b] || !own_kernel(rb) || !same_variant(ra, rb)) continue;
       placed[b] = true;
       for (uint64_t t = 0; t < take[b].second; ++t) ht[n++] = tile_of(rb, rb.next_tile + t);
     }
@@ -283,10 +298,14 @@ hipError_t launch_slice(zmc_server* s, int si, Slice* out) {
   if (e == hipSuccess && n_builtin > n32)
     e = zmc::launch_batch_any(ZMC_FP64, s->d_slots, dt, n32, n_builtin, dc + 1, s->blocks64, st);
   for (size_t gi = 0; e == hipSuccess && gi < groups.size(); ++gi) {
-    const UserGroup& grp = groups[gi];
-    const unsigned blocks = std::max(1u, std::min(grp.first->user_blocks, grp.end - grp.begin));
-    e = zmc::launch_user_batch(grp.first->user, s->d_slots, dt, grp.begin, grp.end, dc + 2 + gi,
-                               blocks, st);
+    const VariantGroup& grp = groups[gi];
+    const zmc_scan_desc& d = grp.first->desc;
+    const unsigned blocks = std::max(1u, std::min(grp.first->own_blocks, grp.end - grp.begin));
+    e = d.family == ZMC_USER
+            ? zmc::launch_user_batch(grp.first->user, s->d_slots, dt, grp.begin, grp.end,
+                                     dc + 2 + gi, blocks, st)
+            : zmc::launch_batch_variant(d.precision, d.family, d.N, s->d_slots, dt, grp.begin,
+                                        grp.end, dc + 2 + gi, blocks, st);
   }
   if (e == hipSuccess && !merges.empty()) {
     // a finishing request's earlier tiles may sit in the other stream's slice
@@ -409,7 +428,14 @@ void run(zmc_server* s) {
           finish(s, r, us != ZMC_OK ? us : ZMC_E_DEVICE);
           continue;
         }
-        r->user_blocks = (unsigned)std::max(1, s->cu * std::max(1, per_cu));
+        r->own_blocks = (unsigned)std::max(1, s->cu * std::max(1, per_cu));
+      } else if (r->desc.N > zmc::kAnyMaxDims) {
+        int per_cu = 0;
+        if (zmc::batch_occupancy(r->desc.precision, r->desc.family, r->desc.N, &per_cu) != hipSuccess) {
+          finish(s, r, ZMC_E_DEVICE);
+          continue;
+        }
+        r->own_blocks = (unsigned)std::max(1, s->cu * std::max(1, per_cu));
       }
       if (admit(s, r, si) != hipSuccess) {
         finish(s, r, ZMC_E_DEVICE);

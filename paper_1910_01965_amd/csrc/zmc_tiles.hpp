@@ -10,17 +10,25 @@
 namespace zmc {
 
 // Waves per SIMD asked of the point-major and batch kernels.  FP32 with
-// N >= 4 runs faster at 8 (the compiler then keeps 64 VGPRs and spills a few
-// set-up values); at N <= 3, and in FP64, its own choice is faster.
-template <typename T, int N> constexpr int kMinWaves = (sizeof(T) == 4 && N >= 4) ? 8 : 1;
+// 4 <= N <= 8 runs faster at 8 (the compiler then keeps 64 VGPRs and spills a
+// few set-up values); at N <= 3, in FP64, and for N > 8 (where 64 VGPRs
+// would spill the per-point constants of every sample) its own choice is
+// taken.
+template <typename T, int N>
+constexpr int kMinWaves = (sizeof(T) == 4 && N >= 4 && N <= kAnyMaxDims) ? 8 : 1;
 
 template <class Fam, typename T, int N>
 __global__ __launch_bounds__(256, (kMinWaves<T, N>)) void k_point_major(ScanParams p) {
   point_major_body<Fam, T, N>(p);
 }
 
+// Threads per sample-major block: up to 1024, or 256 for N > kAnyMaxDims,
+// whose per-point constants and variates need more than the 128 VGPRs that a
+// 1024-thread block leaves each lane.
+template <int N> constexpr int kSmMaxThreads = N > kAnyMaxDims ? 256 : 1024;
+
 template <class Fam, typename T, int N>
-__global__ __launch_bounds__(1024) void k_sample_major(ScanParams p) {
+__global__ __launch_bounds__(kSmMaxThreads<N>) void k_sample_major(ScanParams p) {
   __shared__ double lds[48];
   sample_major_body<Fam, T, N>(p, lds);
 }
@@ -38,14 +46,16 @@ __global__ __launch_bounds__(256, (kMinWaves<T, N>)) void k_batch(const ScanPara
   batch_body<Fam, T, N>(scans, tiles, begin, end, counter, &next, lds);
 }
 
-// One tile of any family and dimension in working precision T: the switch
-// picks the template instance from the scan's own (family, N).
+// One tile of any family with N <= kAnyMaxDims in working precision T: the
+// switch picks the template instance from the scan's own (family, N).  Scans
+// of more dimensions run in their own per-variant kernels (k_batch), so that
+// this kernel's register use stays that of its N <= 8 branches.
 template <typename T>
 __device__ __forceinline__ void run_tile_any(const ScanParams& p, const Tile& tl, double* lds) {
   const uint64_t sp = tl.split_mode & ~kTileSampleMajor;
   const bool sm = (tl.split_mode & kTileSampleMajor) != 0;
 #define ZMC_TILE_CASE(FAM, NN)                                  \
-  case FAM##_ID * 16 + NN:                                      \
+  case FAM##_ID * 32 + NN:                                      \
     if (sm)                                                     \
       sm_tile<FAM<T, NN>, T, NN>(p, tl.first, sp, lds);         \
     else                                                        \
@@ -56,7 +66,8 @@ __device__ __forceinline__ void run_tile_any(const ScanParams& p, const Tile& tl
   ZMC_TILE_CASE(FAM, 5) ZMC_TILE_CASE(FAM, 6) ZMC_TILE_CASE(FAM, 7) ZMC_TILE_CASE(FAM, 8)
   constexpr int SinSum_ID = ZMC_SIN_SUM, Gauss_ID = ZMC_GAUSS, Const_ID = ZMC_CONST,
                 Linear_ID = ZMC_LINEAR, CosExp_ID = ZMC_COSEXP;
-  switch (p.family * 16 + p.N) {
+  static_assert(kAnyMaxDims == 8 && kMaxDims < 32, "the cases list N = 1..8");
+  switch (p.family * 32 + p.N) {
     ZMC_TILE_CASES(SinSum)
     ZMC_TILE_CASES(Gauss)
     ZMC_TILE_CASES(Const)
@@ -71,8 +82,8 @@ __device__ __forceinline__ void run_tile_any(const ScanParams& p, const Tile& tl
 #undef ZMC_TILE_CASE
 }
 
-// Batched scans, one kernel for every family and dimension of one working
-// precision: the blocks pop tiles of all scans from one queue.
+// Batched scans, one kernel for every family (N <= kAnyMaxDims) of one
+// working precision: the blocks pop tiles of all scans from one queue.
 template <typename T>
 __global__ __launch_bounds__(256) void k_batch_any(const ScanParams* __restrict__ scans,
                                                    const Tile* __restrict__ tiles, uint32_t begin,
@@ -97,10 +108,13 @@ __global__ void k_debug_values(ScanParams p, uint64_t g, uint64_t s0, int64_t co
 }
 
 // ---------------------------------------------------------------------------
-// Launchers of one family F in working precision T, for every N; each
-// (family, precision) pair is instantiated in its own translation unit.
+// Launchers of one family F in working precision T for N = Lo .. Lo + 7
+// (Lo = 1 or 9); each (family, precision, N range) triple is instantiated in
+// its own translation unit.
 // ---------------------------------------------------------------------------
-template <template <typename, int> class F, typename T>
+constexpr int kDimsPerUnit = 8;
+
+template <template <typename, int> class F, typename T, int Lo>
 struct FamilyOps {
   template <int N>
   static hipError_t main_n(const ScanParams& p, const Plan& plan, hipStream_t stream) {
@@ -146,46 +160,47 @@ struct FamilyOps {
 
 // Instances below a family's smallest N (COSEXP needs two dimensions) are
 // never built; validation rejects those descriptors before dispatch.
-#define ZMC_BY_DIMS(CALL)                                                           \
-  switch (N) {                                                                      \
-    case 1: if constexpr (1 >= F<T, 1>::kMinDims) return CALL(1); else break;       \
-    case 2: return CALL(2);                                                         \
-    case 3: return CALL(3);                                                         \
-    case 4: return CALL(4);                                                         \
-    case 5: return CALL(5);                                                         \
-    case 6: return CALL(6);                                                         \
-    case 7: return CALL(7);                                                         \
-    case 8: return CALL(8);                                                         \
-    default: break;                                                                 \
-  }                                                                                 \
+#define ZMC_BY_DIMS(CALL)                                                                 \
+  switch (N - Lo) {                                                                       \
+    case 0: if constexpr (Lo >= F<T, Lo>::kMinDims) return CALL(Lo); else break;          \
+    case 1: return CALL(Lo + 1);                                                          \
+    case 2: return CALL(Lo + 2);                                                          \
+    case 3: return CALL(Lo + 3);                                                          \
+    case 4: return CALL(Lo + 4);                                                          \
+    case 5: return CALL(Lo + 5);                                                          \
+    case 6: return CALL(Lo + 6);                                                          \
+    case 7: return CALL(Lo + 7);                                                          \
+    default: break;                                                                       \
+  }                                                                                       \
   return hipErrorInvalidValue;
+static_assert(kDimsPerUnit == 8, "ZMC_BY_DIMS lists eight dimensions");
 
-template <template <typename, int> class F, typename T>
-hipError_t FamilyOps<F, T>::main(int N, const ScanParams& p, const Plan& plan, hipStream_t stream) {
+template <template <typename, int> class F, typename T, int Lo>
+hipError_t FamilyOps<F, T, Lo>::main(int N, const ScanParams& p, const Plan& plan, hipStream_t stream) {
 #define ZMC_CALL(NN) main_n<NN>(p, plan, stream)
   ZMC_BY_DIMS(ZMC_CALL)
 #undef ZMC_CALL
 }
 
-template <template <typename, int> class F, typename T>
-hipError_t FamilyOps<F, T>::values(int N, const ScanParams& p, uint64_t g, uint64_t s0,
-                                   int64_t count, double* out, hipStream_t stream) {
+template <template <typename, int> class F, typename T, int Lo>
+hipError_t FamilyOps<F, T, Lo>::values(int N, const ScanParams& p, uint64_t g, uint64_t s0,
+                                       int64_t count, double* out, hipStream_t stream) {
 #define ZMC_CALL(NN) values_n<NN>(p, g, s0, count, out, stream)
   ZMC_BY_DIMS(ZMC_CALL)
 #undef ZMC_CALL
 }
 
-template <template <typename, int> class F, typename T>
-hipError_t FamilyOps<F, T>::occupancy(int N, int* blocks_per_cu) {
+template <template <typename, int> class F, typename T, int Lo>
+hipError_t FamilyOps<F, T, Lo>::occupancy(int N, int* blocks_per_cu) {
 #define ZMC_CALL(NN) occupancy_n<NN>(blocks_per_cu)
   ZMC_BY_DIMS(ZMC_CALL)
 #undef ZMC_CALL
 }
 
-template <template <typename, int> class F, typename T>
-hipError_t FamilyOps<F, T>::batch(int N, const ScanParams* scans, const Tile* tiles,
-                                  uint32_t begin, uint32_t end, uint32_t* counter,
-                                  unsigned blocks, hipStream_t stream) {
+template <template <typename, int> class F, typename T, int Lo>
+hipError_t FamilyOps<F, T, Lo>::batch(int N, const ScanParams* scans, const Tile* tiles,
+                                      uint32_t begin, uint32_t end, uint32_t* counter,
+                                      unsigned blocks, hipStream_t stream) {
 #define ZMC_CALL(NN) batch_n<NN>(scans, tiles, begin, end, counter, blocks, stream)
   ZMC_BY_DIMS(ZMC_CALL)
 #undef ZMC_CALL
@@ -213,9 +228,11 @@ hipError_t AnyOps<T>::batch(const ScanParams* scans, const Tile* tiles, uint32_t
   return hipGetLastError();
 }
 
-#define ZMC_DECLARE_FAMILY_OPS(F)                 \
-  extern template struct FamilyOps<F, float>;     \
-  extern template struct FamilyOps<F, double>;
+#define ZMC_DECLARE_FAMILY_OPS(F)                                \
+  extern template struct FamilyOps<F, float, 1>;                 \
+  extern template struct FamilyOps<F, double, 1>;                \
+  extern template struct FamilyOps<F, float, 1 + kDimsPerUnit>;  \
+  extern template struct FamilyOps<F, double, 1 + kDimsPerUnit>;
 ZMC_DECLARE_FAMILY_OPS(SinSum)
 ZMC_DECLARE_FAMILY_OPS(Gauss)
 ZMC_DECLARE_FAMILY_OPS(CosExp)

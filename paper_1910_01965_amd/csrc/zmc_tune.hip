@@ -15,12 +15,13 @@
 #include <string>
 
 #include "zmc.h"
+#include "zmc_device.hpp"
 #include "zmc_internal.hpp"
 
 namespace zmc {
 namespace {
 
-constexpr int kFamilies = 5, kPrecisions = 2, kDims = 8;
+constexpr int kFamilies = 5, kPrecisions = 2, kDims = kMaxDims;
 
 struct Table {
   TuneEntry e[kFamilies][kPrecisions][kDims + 1];

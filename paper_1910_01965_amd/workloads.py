@@ -151,19 +151,27 @@ def family_shape(family, N, L, samples, seed, precision="fp32"):
 _FAMILY_M = {"sin_sum": 1, "gauss": 2, "cosexp": 4}
 
 
-def batched_512(count=512, seed=3, precision="fp32"):
+def batched_512(count=512, seed=3, precision="fp32", dims=(2, 8)):
     """The 512-scan batch: family uniform over the three, N uniform in 2..8,
     grid size log-uniform in [1e3, 1e6] (L = max(2, round(G^(1/M))) values per
-    axis), samples uniform over {2^10, ..., 2^18}, Philox seeds 0..count-1."""
+    axis), samples uniform over {2^10, ..., 2^18}, Philox seeds 0..count-1.
+    `dims` = (smallest, largest) N."""
     rng = np.random.default_rng(seed)
     fams = ["sin_sum", "gauss", "cosexp"]
     out = []
     for i in range(count):
         fam = fams[int(rng.integers(0, 3))]
-        N = int(rng.integers(2, 9))
+        N = int(rng.integers(dims[0], dims[1] + 1))
         g_target = float(np.exp(rng.uniform(np.log(1e3), np.log(1e6))))
         M = _FAMILY_M[fam]
         L = max(2, int(round(g_target ** (1.0 / M))))
         samples = 1 << int(rng.integers(10, 19))
         out.append(family_shape(fam, N, L, samples, i, precision))
     return out
+
+
+def batched_wide(count=96, seed=4, precision="fp32"):
+    """Scans shaped like the 512-scan batch with N uniform in 9..16 (the
+    integration dimensions above the any-family kernel's), for tuning and
+    testing those kernels."""
+    return batched_512(count=count, seed=seed, precision=precision, dims=(9, 16))

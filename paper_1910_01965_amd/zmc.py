@@ -30,7 +30,7 @@ EXPORTS = ("zmc_last_error", "zmc_version", "zmc_validate", "zmc_plan", "zmc_sca
            "zmc_server_get_stats", "zmc_server_release", "zmc_server_destroy",
            "zmc_integrand_create",
            "zmc_integrand_log", "zmc_integrand_destroy", "zmc_scan_chunked", "zmc_scan_range",
-           "zmc_debug_valu_probe")
+           "zmc_debug_valu_probe", "zmc_debug_rate_probe")
 
 
 class ZmcError(RuntimeError):
@@ -131,6 +131,7 @@ def load():
         lib.zmc_debug_values.argtypes = [descp, vp, ctypes.c_uint64, ctypes.c_uint64,
                                          ctypes.c_int64, vp, vp]
         lib.zmc_debug_valu_probe.argtypes = [ctypes.c_int32, ctypes.c_int64, vp, vp]
+        lib.zmc_debug_rate_probe.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, vp, vp]
         ptrs = ctypes.POINTER(ctypes.c_void_p)
         lib.zmc_batch_default_opts.argtypes = [ctypes.POINTER(BatchOpts)]
         lib.zmc_batch_default_opts.restype = None
@@ -413,6 +414,20 @@ def debug_valu_probe(blocks, iters, stream=None):
     out = torch.empty(int(blocks) * 256, dtype=torch.float32, device="cuda")
     _check(load().zmc_debug_valu_probe(int(blocks), int(iters), ctypes.c_void_p(out.data_ptr()),
                                        _stream_ptr(stream)))
+    return out
+
+
+RATE_OPS = ("xor_b32", "add_f32", "fma_f32", "mad_u64_u32", "bitop3_b32", "exp_f32", "sin_f32",
+            "fma_f64")
+
+
+def debug_rate_probe(op, blocks, iters, stream=None):
+    """Launch the instruction-rate load of form `op` (a name of RATE_OPS);
+    returns its output tensor (one word per thread)."""
+    import torch
+    out = torch.empty(blocks * 256, dtype=torch.int64, device="cuda")
+    _check(load().zmc_debug_rate_probe(RATE_OPS.index(op), blocks, iters,
+                                       ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
 
 

@@ -56,7 +56,6 @@ GOOD = wl.ScanSpec("gauss", [np.linspace(0.1, 10, 5), np.linspace(0.1, 10, 7)],
     (GOOD.with_(axes=[np.zeros(0), np.linspace(0.1, 10, 7)]), 1),  # an empty axis (G = 0)
     (GOOD.with_(axes=[np.arange(2.0)] * 17), 1),               # M > 16
     (GOOD.with_(lo=np.zeros(17), hi=np.ones(17)), 1),          # N > 16
-    (GOOD.with_(lo=np.zeros(12), hi=np.ones(12)), 4),          # N 9..16: unsupported
     (GOOD.with_(axes=[np.arange(1 << 21, dtype=np.float64)] * 3, family="sin_sum"), 1),  # G > 2^62
 ])
 def test_invalid_descriptors(lib, bad, status):
@@ -72,6 +71,8 @@ def test_valid_descriptors(lib):
     assert zmc.validate(wl.plain_fp64()) == 1000
     assert zmc.validate(wl.gauss_2p()) == 10**6
     assert zmc.validate(wl.cosexp_4p()) == 10**8
+    for N in (9, 12, 16):  # every N up to 16 is built
+        assert zmc.validate(GOOD.with_(lo=np.zeros(N), hi=np.ones(N))) == 35
     assert lib.zmc_last_error().decode() == ""
 
 
@@ -335,3 +336,14 @@ def test_tune_table_source():
     expected = os.path.join(os.path.dirname(zmc.LIB_PATH), "tune_table.txt")
     assert os.path.realpath(runs["default"]) == os.path.realpath(expected)
     assert runs["missing"] == "built-in defaults"
+
+
+def test_wide_scans_take_at_most_256_threads_per_block(lib):
+    """N > 8: sample-major blocks of more than 256 threads are refused (their
+    kernels are built for 256), host-only with an explicit CU count."""
+    sp = GOOD.with_(lo=np.zeros(12), hi=np.ones(12))
+    with pytest.raises(zmc.ZmcError) as ei:
+        zmc.plan(sp, mode="sample_major", block=512, cu_count=256)
+    assert ei.value.status == 1 and "256" in str(ei.value)
+    assert zmc.plan(sp, mode="sample_major", block=256, cu_count=256)["block"] == 256
+    assert zmc.plan(GOOD, mode="sample_major", block=1024, cu_count=256)["block"] == 1024
