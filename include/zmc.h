@@ -85,8 +85,10 @@ typedef struct zmc_scan_desc {
   int32_t M;                /* number of parameters                          */
   int32_t N;                /* integration dimensions                        */
   const int64_t* axis_len;  /* [M] list lengths L_l                          */
-  const double* axis_vals;  /* [sum L_l] host copy of the lists, back to back;
-                               may be NULL for zmc_scan_device              */
+  const double* axis_vals;  /* [sum L_l] host copy of the lists, back to back
+                               (finite values; f and sigma are unspecified
+                               for points with a non-finite one); may be
+                               NULL for zmc_scan_device                     */
   const double* lo;         /* [N] lower box edges                           */
   const double* hi;         /* [N] upper box edges                           */
   int32_t family;           /* zmc_family                                    */

@@ -257,31 +257,58 @@ __device__ __forceinline__ float cos_turns(float r) {
 //        sin a; exact, since 1/4 <= |t| <= 1/2);
 //   cos: v = 1/4 - |t| (cos a = sin(pi/2 - a); exact for |t| >= 1/8, else
 //        one rounding of at most 2^-55 revolutions).
-// x = 2 pi v lies in [-pi/2, pi/2], where the Taylor polynomial of sin
-// through x^21 (Horner in x^2, coefficients (-1)^k / (2k+1)!) truncates below
-// 1.3e-18.  One polynomial serves both functions, with no octant selection.
-__device__ __forceinline__ double sin_2pi_quarter(double v) {
-  const double x = v * 6.283185307179586476925286766559;
-  const double x2 = x * x;
-  double p = 1.9572941063391263e-20;       // 1/21!, then Horner down to -1/3!
-  p = __builtin_fma(p, x2, -8.22063524662433e-18);
-  p = __builtin_fma(p, x2, 2.8114572543455206e-15);
-  p = __builtin_fma(p, x2, -7.647163731819816e-13);
-  p = __builtin_fma(p, x2, 1.6059043836821613e-10);
-  p = __builtin_fma(p, x2, -2.505210838544172e-08);
-  p = __builtin_fma(p, x2, 2.7557319223985893e-06);
-  p = __builtin_fma(p, x2, -0.0001984126984126984);
-  p = __builtin_fma(p, x2, 0.008333333333333333);
-  p = __builtin_fma(p, x2, -0.16666666666666666);
-  return __builtin_fma(p * x2, x, x);
+// sin(2 pi v) = v P(v^2) with P of degree 8, from Chebyshev economization of
+// the Taylor series on [-1/4, 1/4] (paper_1910_01965_amd/fp64_poly.py: the
+// dropped terms are below 1.7e-19, the FP64 Horner evaluation within 2.2e-16
+// relative of a 60-digit reference on a dense grid).  One polynomial serves
+// both functions, with no octant selection.
+__host__ __device__ __forceinline__ double sin_2pi_quarter(double v) {
+  const double v2 = v * v;
+  double p = 0.10071467531221244;
+  p = __builtin_fma(p, v2, -0.7176853699001249);
+  p = __builtin_fma(p, v2, 3.8199227975201033);
+  p = __builtin_fma(p, v2, -15.094641368684599);
+  p = __builtin_fma(p, v2, 42.05869391526577);
+  p = __builtin_fma(p, v2, -76.70585975263434);
+  p = __builtin_fma(p, v2, 81.60524927607172);
+  p = __builtin_fma(p, v2, -41.34170224039975);
+  p = __builtin_fma(p, v2, 6.283185307179586);
+  return v * p;
 }
 
-__device__ __forceinline__ double sin_turns(double r) {
+// FP64 2^t.  k = rint(t) and f = t - k in [-1/2, 1/2] (exact); 2^f by a
+// degree-11 polynomial from Chebyshev economization of the Taylor series of
+// e^(f ln 2) on [-1/2, 1/2] (fp64_poly.py: dropped terms below 3.2e-18,
+// Horner within 1.2e-16 relative); 2^k applied by ldexp.  t is first clamped
+// to [-2100, 2100], beyond which 2^t is 0 or inf in double: -inf then gives
+// 0 and +inf gives inf, as exp does, and k always fits an int (a NaN t is
+// clamped too and gives 0; the parameter values it would come from must be
+// finite).
+__host__ __device__ __forceinline__ double exp2_fp64(double t) {
+  t = __builtin_fmin(__builtin_fmax(t, -2100.0), 2100.0);
+  const double k = __builtin_rint(t);
+  const double f = t - k;
+  double p = 4.456675463639861e-10;
+  p = __builtin_fma(p, f, 7.074194562613105e-09);
+  p = __builtin_fma(p, f, 1.0178051192117847e-07);
+  p = __builtin_fma(p, f, 1.3215432534254118e-06);
+  p = __builtin_fma(p, f, 1.5252733856295574e-05);
+  p = __builtin_fma(p, f, 0.00015403530463727982);
+  p = __builtin_fma(p, f, 0.001333355814639035);
+  p = __builtin_fma(p, f, 0.009618129107587253);
+  p = __builtin_fma(p, f, 0.0555041086648217);
+  p = __builtin_fma(p, f, 0.24022650695910158);
+  p = __builtin_fma(p, f, 0.6931471805599453);
+  p = __builtin_fma(p, f, 1.0);
+  return __builtin_ldexp(p, (int)k);
+}
+
+__host__ __device__ __forceinline__ double sin_turns(double r) {
   const double t = r - __builtin_rint(r);
   return sin_2pi_quarter(__builtin_fabs(t) > 0.25 ? __builtin_copysign(0.5, t) - t : t);
 }
 
-__device__ __forceinline__ double cos_turns(double r) {
+__host__ __device__ __forceinline__ double cos_turns(double r) {
   const double t = r - __builtin_rint(r);
   return sin_2pi_quarter(0.25 - __builtin_fabs(t));
 }
@@ -410,7 +437,7 @@ template <typename T, int N> struct Gauss {
 template <typename T, int N> struct CosExp {
   static constexpr int kMinDims = 2;
   T A[N], B[N];
-  T x1, x2, nx3sq, x4;  // nx3sq = -x3^2 (FP32: times log2(e))
+  T x1, x2, nx3sq, x4;  // nx3sq = -x3^2 log2(e): the exponential is evaluated as 2^t
   T rest;               // FP32: sum of B_k for k >= 3, folded into the phase
   // x1, x2, rest and A_k, B_k (k >= 3) in revolutions (times 1/(2 pi))
   __device__ void setup(const ScanParams& p, uint64_t g) {
@@ -427,7 +454,7 @@ template <typename T, int N> struct CosExp {
     x1 = (T)(param_x(p, g, 0) * turn);
     x2 = (T)(param_x(p, g, 1) * turn);
     const double x3 = param_x(p, g, 2);
-    nx3sq = sizeof(T) == 8 ? (T)(-(x3 * x3)) : (T)(-(x3 * x3) * kLog2e);
+    nx3sq = (T)(-(x3 * x3) * kLog2e);
     x4 = (T)param_x(p, g, 3);
     rest = (T)(sb * turn);
   }
@@ -438,7 +465,7 @@ template <typename T, int N> struct CosExp {
       double ph = x1 * y1 + x2 * y2;
 #pragma unroll
       for (int k = 2; k < N; ++k) ph += fmaT(A[k], t[k], B[k]);
-      return cos_turns(ph) * exp(nx3sq * y1 * y2) + x4;
+      return __builtin_fma(cos_turns(ph), exp2_fp64(nx3sq * y1 * y2), x4);
     } else {
       float ph;
       if constexpr (N == 2) {

@@ -67,7 +67,11 @@ def test_paper_table1_delta_r():
     |f_th|).  The printed values sit at 1/sqrt(10) of what crude MC gives at
     the stated 10^4 samples in 13 of the 16 cells; they match 10^5 samples.
     So the oracle runs 10^5 samples; its dr must then lie within the spread
-    dr has for crude MC (from the exact variances) of the printed value."""
+    dr has for crude MC (from the exact variances) of the printed value.
+    Context, not a pin: the paper's generator is unknown and the sample count
+    is chosen to fit the column, so this only shows that the oracle's crude
+    MC lands where the paper's did; the closed-form, quadrature and
+    known-answer tests are what pin the oracle."""
     printed = {1: 0.02512, 2: 0.25034, 3: 1.19949, 4: 6.19901}
     n = 100_000
     for N, p in printed.items():
