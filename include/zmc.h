@@ -408,6 +408,13 @@ typedef struct zmc_server_opts {
   int32_t max_wait_ms;         /* ZMC_ADMIT_SHORTEST only: a request queued
                                   longer than this is admitted before any
                                   shorter one, oldest first (0 = no bound)    */
+  int32_t slice_us;            /* > 0: size slices for about this much device
+                                  time in microseconds: slices take
+                                  slice_samples until the server has measured
+                                  the device's throughput on them, then that
+                                  throughput times slice_us (a slice never
+                                  lasts less than its longest tile); 0 = every
+                                  slice takes slice_samples                  */
 } zmc_server_opts;
 
 /* Admission order.  Arrival order (FIFO) gives every request the same queueing
@@ -438,11 +445,12 @@ typedef struct zmc_server_stats {
   double samples_per_s;
   uint64_t tickets;            /* requests still tracked: submitted and not yet
                                   released with zmc_server_release           */
+  uint64_t slice_samples_now;  /* the sample budget of the next slice        */
 } zmc_server_stats;
 
 /* Starts the scheduler thread on the current device (opts may be NULL for
- * all defaults; max_slots > 65536, max_inflight > 16, an unknown admission
- * or a negative max_wait_ms give ZMC_E_INVALID).  submit, poll, wait
+ * all defaults; max_slots > 65536, max_inflight > 16, an unknown admission,
+ * a negative max_wait_ms or a negative slice_us give ZMC_E_INVALID).  submit, poll, wait
  * and get_stats may be called from any number of threads at once; destroy
  * must not overlap any other call on the same server, and the handle is
  * invalid once it has returned. */

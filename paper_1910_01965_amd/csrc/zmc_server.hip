@@ -69,7 +69,14 @@ using ReqPtr = std::shared_ptr<Request>;
 struct Slice {
   hipEvent_t done_ev = nullptr;
   std::vector<ReqPtr> finishing;
+  uint64_t samples = 0;        // samples of the slice's tiles
+  Clock::time_point t_launch;  // when it was enqueued
 };
+
+// slice_us: slices of slice_samples samples until the device's throughput has
+// been measured, then that throughput times slice_us, kept within these bounds
+constexpr uint64_t kMinSliceSamples = (uint64_t)1 << 24;
+constexpr uint64_t kMaxSliceSamples = (uint64_t)1 << 44;
 
 constexpr int kStreams = 2;
 // The latency percentiles cover the most recent completions only, so that a
@@ -115,6 +122,11 @@ struct zmc_server {
   std::vector<int> free_slots;
   uint64_t bytes_in_use = 0;
   uint64_t slice_count = 0;
+  uint64_t slice_budget = 0;        // samples of the next slice
+  double rate = 0.0;                // slice_us only: measured samples/s of the device
+  Clock::time_point t_last_retire;  // when the previous slice was seen done
+  uint64_t acc_samples = 0, acc_slices = 0;  // retirements of the current window
+  double acc_seconds = 0.0;
   std::thread thread;
 };
 
@@ -215,7 +227,7 @@ bool same_variant(const Request& a, const Request& b) {
 // point's sample piece to 256 points' pieces.
 hipError_t launch_slice(zmc_server* s, int si, Slice* out) {
   const uint64_t cap = (uint64_t)s->opts.slice_tiles;
-  const uint64_t budget = s->opts.slice_samples;
+  const uint64_t budget = s->slice_budget;
   const int ring_slot = (int)(s->slice_count % (uint64_t)s->ring);
   zmc::Tile* ht = s->h_tiles + (size_t)ring_slot * cap;
   std::vector<std::pair<ReqPtr, uint64_t>> take;
@@ -319,13 +331,51 @@ hipError_t launch_slice(zmc_server* s, int si, Slice* out) {
   }
   if (e == hipSuccess) e = hipEventRecord(s->done_events[ring_slot], st);
   out->done_ev = s->done_events[ring_slot];
+  out->samples = used_samples;
+  out->t_launch = Clock::now();
   std::lock_guard<std::mutex> lk(s->mu);
   s->stats.slices++;
+  s->stats.slice_samples_now = s->slice_budget;
   s->stats.tiles += n;
   return e;
 }
 
+// slice_us: the device's throughput is measured on slices of at least
+// slice_samples samples (the default budget, enough tiles to keep the device
+// busy with two slices in flight), as the samples such slices retire over the
+// time they take, in windows of at least kRateWindow seconds and four slices
+// (several slices are often seen done at once).  Each window updates an
+// exponential average, and the budget becomes that rate times slice_us.
+// Smaller slices are left out: a slice shorter than a tile's duration is
+// bound by the tile, not by the device's throughput, and counting it would
+// shrink the budget further.
+constexpr double kRateWindow = 0.02;  // seconds
+
+void update_slice_budget(zmc_server* s, const Slice& sl) {
+  const Clock::time_point now = Clock::now();
+  const Clock::time_point start = std::max(sl.t_launch, s->t_last_retire);
+  s->t_last_retire = now;
+  if (s->opts.slice_us <= 0) return;
+  if (sl.samples < s->opts.slice_samples) {  // a small slice ends the window
+    s->acc_samples = s->acc_slices = 0;
+    s->acc_seconds = 0.0;
+    return;
+  }
+  s->acc_samples += sl.samples;
+  s->acc_slices += 1;
+  s->acc_seconds += std::max(0.0, std::chrono::duration<double>(now - start).count());
+  if (s->acc_seconds < kRateWindow || s->acc_slices < 4) return;
+  const double r = (double)s->acc_samples / s->acc_seconds;
+  s->acc_samples = s->acc_slices = 0;
+  s->acc_seconds = 0.0;
+  s->rate = s->rate > 0.0 ? 0.5 * s->rate + 0.5 * r : r;
+  const double want = s->rate * 1e-6 * (double)s->opts.slice_us;
+  s->slice_budget = (uint64_t)std::min<double>((double)kMaxSliceSamples,
+                                               std::max<double>((double)kMinSliceSamples, want));
+}
+
 void retire(zmc_server* s, Slice& sl) {
+  update_slice_budget(s, sl);
   for (const ReqPtr& r : sl.finishing) {
     if (r->dmem) (void)hipFreeAsync(r->dmem, s->streams[r->alloc_stream]);
     r->dmem = nullptr;
@@ -527,6 +577,10 @@ zmc_status zmc_server_create(const zmc_server_opts* opts, zmc_server** out) {
     return fail(ZMC_E_INVALID, "admission must be ZMC_ADMIT_FIFO or ZMC_ADMIT_SHORTEST and "
                 "max_wait_ms >= 0");
   }
+  if (o.slice_us < 0) {
+    delete s;
+    return fail(ZMC_E_INVALID, "slice_us = %d < 0", o.slice_us);
+  }
   s->ring = o.max_inflight + 1;
   hipError_t e = hipGetDevice(&s->device);
   int cu = o.cu_count;
@@ -545,6 +599,7 @@ zmc_status zmc_server_create(const zmc_server_opts* opts, zmc_server** out) {
   s->blocks64 = (unsigned)std::max(1, cu * std::max(1, per64));
   if (o.slice_tiles <= 0) o.slice_tiles = (int32_t)std::min<uint64_t>(64ull * s->blocks32, 1u << 20);
   if (o.slice_samples == 0) o.slice_samples = 4000000000ull;
+  s->slice_budget = o.slice_samples;
   const size_t cap = (size_t)o.slice_tiles, ring = (size_t)s->ring, slots = (size_t)o.max_slots;
   const size_t off_tiles = align_up(sizeof(zmc::ScanParams) * slots);
   const size_t off_counters = off_tiles + align_up(sizeof(zmc::Tile) * cap * ring);

@@ -89,7 +89,8 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
                 ("slice_tiles", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
                 ("cu_count", ctypes.c_int32), ("slice_samples", ctypes.c_uint64),
-                ("admission", ctypes.c_int32), ("max_wait_ms", ctypes.c_int32)]
+                ("admission", ctypes.c_int32), ("max_wait_ms", ctypes.c_int32),
+                ("slice_us", ctypes.c_int32)]
 
 ADMISSION = {"fifo": 0, "shortest": 1}
 
@@ -99,7 +100,8 @@ class ServerStats(ctypes.Structure):
         "submitted", "admitted", "completed", "failed", "pending", "active", "samples_completed",
         "slices", "tiles", "bytes_in_use", "bytes_peak")] + [
         (k, ctypes.c_double) for k in ("latency_p50_s", "latency_p99_s", "latency_max_s",
-                                       "samples_per_s")] + [("tickets", ctypes.c_uint64)]
+                                       "samples_per_s")] + [("tickets", ctypes.c_uint64),
+                                                            ("slice_samples_now", ctypes.c_uint64)]
 
 
 _lib = None
@@ -568,9 +570,10 @@ class Server:
     must not be in use by pending work on other streams when submitted."""
 
     def __init__(self, hbm_budget_bytes=0, max_slots=0, slice_tiles=0, max_inflight=0, cu_count=0,
-                 slice_samples=0, admission="fifo", max_wait_ms=0):
+                 slice_samples=0, admission="fifo", max_wait_ms=0, slice_us=0):
         o = ServerOpts(int(hbm_budget_bytes), int(max_slots), int(slice_tiles), int(max_inflight),
-                       int(cu_count), int(slice_samples), ADMISSION[admission], int(max_wait_ms))
+                       int(cu_count), int(slice_samples), ADMISSION[admission], int(max_wait_ms),
+                       int(slice_us))
         h = ctypes.c_void_p()
         _check(load().zmc_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h

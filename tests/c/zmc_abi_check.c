@@ -134,6 +134,7 @@ static void device_checks(const double* gauss_vals, const int64_t* gauss_len) {
              ss.samples_per_s > 0.0,
          "zmc_server_get_stats: counts, latency percentiles, throughput");
   expect(ss.tickets == (uint64_t)NS, "zmc_server_get_stats: every ticket still tracked");
+  expect(ss.slice_samples_now == 4000000000ull, "zmc_server_get_stats: default slice budget");
   for (int i = 0; i < NS; ++i)
     expect(zmc_server_release(srv, t[i]) == ZMC_OK, "zmc_server_release of a finished request");
   {

@@ -317,6 +317,10 @@ def test_server_rejects_bad_admission_options(lib):
         assert lib.zmc_server_create(ctypes.byref(o), ctypes.byref(out)) == 1
         assert b"admission" in lib.zmc_last_error()
         assert not out.value
+    o = zmc.ServerOpts(0, 0, 0, 0, 0, 0, 0, 0, -1)
+    assert lib.zmc_server_create(ctypes.byref(o), ctypes.byref(out)) == 1
+    assert b"slice_us" in lib.zmc_last_error()
+    assert not out.value
 
 
 def test_tune_table_source():

@@ -306,3 +306,33 @@ def test_released_requests_hold_no_memory():
          f"{torch.cuda.memory_allocated() - mem0} B at the end")
     assert peak <= 34 * 2 * 16 * base.G * 2  # at most the live requests' f and sigma (+ cache rounding)
     assert torch.cuda.memory_allocated() - mem0 <= 2 * 16 * base.G * 4
+
+
+def test_slice_duration_target():
+    """slice_us sizes slices by device time (samples at the measured rate):
+    the same requests run in many more, smaller slices at a 1 ms target than
+    at a 16 ms one, with bitwise the same results."""
+    import torch
+    zmc = _zmc()
+    specs = _requests(24, seed=9, max_samples=1 << 16)
+    runs = {}
+    for us in (1000, 16000):
+        srv = zmc.Server(slice_us=us)
+        tickets = [srv.submit(sp) for sp in specs]
+        for t in tickets:
+            assert srv.wait(t)[0] == 0
+        stats = srv.stats()
+        outs = [srv.outputs(t) for t in tickets]
+        srv.close()
+        torch.cuda.synchronize()
+        runs[us] = (stats, [(f.cpu().numpy(), s.cpu().numpy()) for f, s in outs])
+        _say(f"slice_us={us}: {stats['slices']} slices, next slice {stats['slice_samples_now']:.3g} "
+             f"samples, {stats['samples_per_s']:.3g} samples/s")
+    short, long_ = runs[1000][0], runs[16000][0]
+    assert short["slices"] >= 2 * long_["slices"], (short["slices"], long_["slices"])
+    assert long_["slice_samples_now"] >= 4 * short["slice_samples_now"]
+    for (fa, sa), (fb, sb) in zip(runs[1000][1], runs[16000][1]):
+        assert np.array_equal(fa, fb) and np.array_equal(sa, sb)
+    for i in (0, 7):
+        fa, sa = _alone(specs[i])
+        assert np.array_equal(runs[1000][1][i][0], fa) and np.array_equal(runs[1000][1][i][1], sa)
