@@ -283,9 +283,12 @@ __host__ __device__ __forceinline__ double sin_2pi_quarter(double v) {
 // to [-2100, 2100], beyond which 2^t is 0 or inf in double: -inf then gives
 // 0 and +inf gives inf, as exp does, and k always fits an int (a NaN t is
 // clamped too and gives 0; the parameter values it would come from must be
-// finite).
+// finite).  kNonPositive: the caller guarantees t <= 0 (or NaN), so only the
+// lower clamp is needed.
+template <bool kNonPositive = false>
 __host__ __device__ __forceinline__ double exp2_fp64(double t) {
-  t = __builtin_fmin(__builtin_fmax(t, -2100.0), 2100.0);
+  t = __builtin_fmax(t, -2100.0);
+  if constexpr (!kNonPositive) t = __builtin_fmin(t, 2100.0);
   const double k = __builtin_rint(t);
   const double f = t - k;
   double p = 4.456675463639861e-10;
@@ -377,7 +380,7 @@ template <typename T, int N> struct GaussUnit {
       q = k == 0 ? z * z : fmaT(z, z, q);
     }
     if constexpr (sizeof(T) == 8) {
-      return exp(-q);
+      return exp2_fp64<true>(q * -kLog2e);  // q, a sum of squares, is >= 0
     } else {
       return __builtin_amdgcn_exp2f(-q);
     }
@@ -426,7 +429,7 @@ template <typename T, int N> struct Gauss {
       q = k == 0 ? (c[k] * y) * y : fmaT(c[k] * y, y, q);
     }
     if constexpr (sizeof(T) == 8) {
-      return exp(-q);
+      return exp2_fp64(q * -kLog2e);
     } else {
       return __builtin_amdgcn_exp2f(-q);
     }

@@ -43,6 +43,12 @@ int main() {
   bad += !(zmc::exp2_fp64(-1074.0) == ldexp(1.0, -1074));
   bad += !(zmc::exp2_fp64(1023.0) == ldexp(1.0, 1023));
   bad += !(zmc::sin_turns(0.25) == 1.0 && zmc::cos_turns(0.0) == 1.0);
+  // the variant for t <= 0 (the Gaussian's -q log2 e)
+  for (int i = 0; i <= 100000; ++i) {
+    const double t = -i * (60.0 / 100000.0);
+    bad += !(zmc::exp2_fp64<true>(t) == zmc::exp2_fp64(t));
+  }
+  bad += !(zmc::exp2_fp64<true>(-INFINITY) == 0.0 && zmc::exp2_fp64<true>(-1.0e300) == 0.0);
   printf("%.3e %.3e %.3e %d\n", worst_e, worst_s, worst_c, bad);
   return 0;
 }
