@@ -315,7 +315,7 @@ extern "C" {
 
 const char* zmc_last_error(void) { return g_err; }
 
-const char* zmc_version(void) { return "zmc 0.8 gfx950"; }
+const char* zmc_version(void) { return "zmc 0.9 gfx950"; }
 
 zmc_status zmc_validate(const zmc_scan_desc* desc, uint64_t* grid_points) {
   return validate(desc, grid_points);

@@ -1,7 +1,7 @@
 """User integrands compiled at run time (hipRTC) against the oracle, which
 compiles the same source text as host C++ (needs an MI355X).  The FP64 path
 must meet the 1e-12 bar, the FP32 path the FP32 bar, in both kernel layouts,
-for several N, M and constant vectors."""
+for several N (up to 16), M and constant vectors."""
 import sys
 
 import numpy as np
@@ -50,7 +50,7 @@ def _say(msg):
 
 def _cases(precision):
     out = []
-    for N in (1, 3, 8):
+    for N in (1, 3, 8, 12, 16):  # 12 and 16: the per-variant kernels of N > 8
         out.append(wl.ScanSpec("user", [np.linspace(0.2, 3, 9)], np.zeros(N), np.linspace(1, 2, N),
                                2051, 21, precision, name=f"wave N{N}", source=WAVE % N,
                                params=np.array([0.7, 0.3, 1.5])))
