@@ -546,6 +546,22 @@ def left(args):
     return args.time_budget - (time.perf_counter() - T_START)
 
 
+def fit_serving_window(asked, left_s, cap, plain, short_s, trace_samples):
+    """The arrival window to run: `asked` seconds, halved (down to 4 s) while
+    the serving section would not fit in `left_s` seconds.  Its cost: serving
+    the trace (never shorter than its arrivals) at `cap` samples/s, the same
+    trace as plain launches at `plain` samples/s, the two short runs and 30 s
+    of margin."""
+    def cost(sec):
+        tot = trace_samples(sec)
+        return max(sec, tot / cap) + tot / plain + 2.5 * short_s + 30.0
+
+    seconds = asked
+    while seconds > 4.0 and cost(seconds) > left_s:
+        seconds = max(4.0, seconds / 2)
+    return seconds
+
+
 def serving_section(args, out):
     """The serving workload as specified (Poisson arrivals at 200 req/s for
     --serve-seconds, seed 7, 64 GiB budget, arrival order) with the same
@@ -565,13 +581,8 @@ def serving_section(args, out):
         k = int(np.sum(t < sec))
         return sum(sp.G * sp.samples for sp in wl.batched_512(count=k, seed=7))
 
-    def cost(sec):  # serve (never shorter than the arrivals) + plain replay + short runs
-        tot = trace_samples(sec)
-        return max(sec, tot / cap) + tot / plain + 2.5 * short_s + 30.0
-
     asked = seconds
-    while seconds > 4.0 and cost(seconds) > left(args):
-        seconds = max(4.0, seconds / 2)
+    seconds = fit_serving_window(asked, left(args), cap, plain, short_s, trace_samples)
     if seconds != asked:
         log(f"serving: {asked} s of arrivals would not fit the time budget; running {seconds} s")
     log(f"serving: 200 req/s for {seconds} s (arrival order), then the same trace as plain launches")

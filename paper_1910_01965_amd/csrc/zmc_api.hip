@@ -297,6 +297,112 @@ void fill_scan_params(const zmc_scan_desc* d, uint64_t G, const Plan& pl, const 
 
 namespace {
 
+// ---------------------------------------------------------------------------
+// Split-partial workspaces of zmc_scan_device(_ex).  The stream-ordered
+// allocator of this ROCm makes the calling thread wait, at hipMallocAsync /
+// hipFreeAsync, for the device work that last used the block it hands out
+// (measured: each call's enqueue then lasts as long as the previous call's
+// kernels), so back-to-back scans would be serialised on the host.  Outside
+// stream capture, workspaces of up to kMaxCachedWorkspace bytes therefore come
+// from a small per-device cache, without a host wait: each buffer carries an
+// event recorded after the last kernel that uses it and that kernel's stream.
+// A call takes, among the buffers large enough, one whose event has completed;
+// else one last used on the same stream; else a new one while the device holds
+// fewer than kMaxCachedBuffers; else any.  A buffer whose event is pending is
+// ordered after that event on the device (hipStreamWaitEvent), never on the
+// host.  Larger workspaces, whose scans take far longer than that host wait,
+// and every call under capture (where the graph must own its memory as graph
+// memory nodes) use the stream-ordered allocator.
+// ---------------------------------------------------------------------------
+struct Workspace {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;   // recorded after the last kernel that used the buffer
+  hipStream_t last = nullptr;  // the stream that kernel was launched on
+  bool used = false;           // `done` has been recorded
+};
+
+struct DeviceWorkspaces {
+  std::vector<Workspace> idle;  // buffers not held by a call
+  int count = 0;                // idle + held
+};
+
+constexpr int kMaxWsDevices = 64;
+constexpr size_t kMaxCachedWorkspace = (size_t)256 << 20;  // bytes of one cached buffer
+constexpr int kMaxCachedBuffers = 4;                        // buffers per device, held ones included
+std::mutex g_ws_mu;
+DeviceWorkspaces g_ws[kMaxWsDevices];
+
+// A workspace of at least `bytes` on device `dev` (the current device), usable
+// by kernels launched on `s` once this returns.
+hipError_t ws_acquire(int dev, size_t bytes, hipStream_t s, Workspace* out) {
+  Workspace drop;  // a too-small idle buffer freed to keep the count bounded
+  bool reuse = false;
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    DeviceWorkspaces& D = g_ws[dev];
+    std::vector<Workspace>& L = D.idle;
+    auto pick = [&](auto&& ok) {
+      int best = -1;
+      for (int i = 0; i < (int)L.size(); ++i)
+        if (L[i].bytes >= bytes && (best < 0 || L[i].bytes < L[best].bytes) && ok(L[i])) best = i;
+      return best;
+    };
+    int i = pick([](const Workspace& w) { return !w.used || hipEventQuery(w.done) == hipSuccess; });
+    if (i < 0) i = pick([&](const Workspace& w) { return w.last == s; });
+    if (i < 0 && D.count >= kMaxCachedBuffers) i = pick([](const Workspace&) { return true; });
+    if (i >= 0) {
+      *out = L[i];
+      L.erase(L.begin() + i);
+      reuse = true;
+    } else {
+      if (D.count >= kMaxCachedBuffers && !L.empty()) {  // none fits: retire the smallest
+        int j = 0;
+        for (int k = 1; k < (int)L.size(); ++k)
+          if (L[k].bytes < L[j].bytes) j = k;
+        drop = L[j];
+        L.erase(L.begin() + j);
+        --D.count;
+      }
+      ++D.count;
+    }
+  }
+  if (reuse) {
+    if (out->used && hipEventQuery(out->done) != hipSuccess) return hipStreamWaitEvent(s, out->done, 0);
+    return hipSuccess;
+  }
+  if (drop.ptr != nullptr) {  // hipFree waits for the device work that may still use it
+    (void)hipEventDestroy(drop.done);
+    (void)hipFree(drop.ptr);
+  }
+  Workspace w;
+  w.bytes = bytes;
+  hipError_t e = hipMalloc(&w.ptr, bytes);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&w.done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (w.ptr) (void)hipFree(w.ptr);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    --g_ws[dev].count;
+    return e;
+  }
+  *out = w;
+  return hipSuccess;
+}
+
+// Hands a workspace back once the last kernel that uses it is enqueued on `s`.
+hipError_t ws_release(int dev, Workspace w, hipStream_t s) {
+  hipError_t e = hipEventRecord(w.done, s);
+  if (e != hipSuccess) {  // no event to order on: let the buffer's work finish first
+    const hipError_t e2 = hipStreamSynchronize(s);
+    (void)e2;
+  }
+  w.last = s;
+  w.used = e == hipSuccess;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  g_ws[dev].idle.push_back(w);
+  return e;
+}
+
 void to_info(const zmc::Plan& pl, uint64_t G, zmc_plan_info* out) {
   memset(out, 0, sizeof(*out));
   out->mode = pl.mode;
@@ -351,10 +457,23 @@ zmc_status zmc_scan_device_ex(const zmc_scan_desc* desc, const double* d_axis_va
   zmc::ScanParams p;
   fill_params(desc, G, pl, d_axis_vals, d_f, d_sigma, &p);
   hipStream_t s = (hipStream_t)stream;
-  void* ws = nullptr;
+  void* ws = nullptr;       // stream-ordered workspace
+  Workspace cached;         // or one from the per-device cache
+  int dev = 0;
   if (pl.workspace_bytes > 0) {
-    ZMC_HIP(hipMallocAsync(&ws, pl.workspace_bytes, s));
-    p.part_mean = (double*)ws;
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    ZMC_HIP(hipStreamIsCapturing(s, &capture));
+    int stream_dev = 0;
+    ZMC_HIP(hipGetDevice(&dev));
+    ZMC_HIP(hipStreamGetDevice(s, &stream_dev));
+    if (capture == hipStreamCaptureStatusNone && pl.workspace_bytes <= kMaxCachedWorkspace &&
+        dev == stream_dev && dev >= 0 && dev < kMaxWsDevices) {
+      ZMC_HIP(ws_acquire(dev, pl.workspace_bytes, s, &cached));
+      p.part_mean = (double*)cached.ptr;
+    } else {
+      ZMC_HIP(hipMallocAsync(&ws, pl.workspace_bytes, s));
+      p.part_mean = (double*)ws;
+    }
     p.part_m2 = p.part_mean + (uint64_t)pl.splits * G;
   }
   hipEvent_t ev_b = opts ? (hipEvent_t)opts->ev_begin : nullptr;
@@ -363,6 +482,10 @@ zmc_status zmc_scan_device_ex(const zmc_scan_desc* desc, const double* d_axis_va
                                            : zmc::launch_scan(p, pl, desc->precision, s, ev_b, ev_e);
   if (ws != nullptr) {
     hipError_t e2 = hipFreeAsync(ws, s);
+    if (e == hipSuccess) e = e2;
+  }
+  if (cached.ptr != nullptr) {
+    hipError_t e2 = ws_release(dev, cached, s);
     if (e == hipSuccess) e = e2;
   }
   if (e != hipSuccess) return fail(ZMC_E_DEVICE, "scan launch failed: %s", hipGetErrorString(e));

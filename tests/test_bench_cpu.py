@@ -19,3 +19,18 @@ def test_ops_per_sample_of_the_benchmark_integrand():
     import bench
     assert bench.valu_ops_per_sample("gauss", 3) == 30 + 6 + 7 + 8
     assert bench.valu_ops_per_sample("cosexp", 2) == 20 + 4 + 7 + 8
+
+
+def test_serving_window_fits_the_time_budget():
+    # 200 req/s of ~8.6e9-sample requests: about 1.7e12 samples per second of arrivals
+    sys.path.insert(0, ROOT)
+    import bench
+
+    def trace(sec):
+        return 1.72e12 * sec
+
+    # 60 s of arrivals: 1.03e14 samples, ~145 s served and ~145 s replayed at 7.1e11/s
+    assert bench.fit_serving_window(60.0, 470.0, 7.1e11, 7.1e11, 4.0, trace) == 60.0
+    # less time left: the window halves until the section fits, never below 4 s
+    assert bench.fit_serving_window(60.0, 250.0, 7.1e11, 7.1e11, 4.0, trace) == 30.0
+    assert bench.fit_serving_window(60.0, 10.0, 7.1e11, 7.1e11, 4.0, trace) == 4.0

@@ -1,0 +1,81 @@
+"""Split-partial workspaces of zmc_scan_device are reused across calls without a
+host wait (needs an MI355X): many scans with split partials, enqueued back to
+back on one stream and interleaved on two streams with no synchronisation in
+between, and with workspaces that grow past the number of buffers kept per
+device, each equal bit for bit to the same scan run alone."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1910_01965_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_01965_amd import zmc
+    zmc.load()
+    return torch
+
+
+def _specs():
+    # workspaces of 16 * splits * G bytes: 0.6 to 14 MB, growing call by call
+    return [wl.gauss_2p(points_per_axis=100 + 90 * i, samples=8192 + 17 * i, precision="fp32")
+            for i in range(6)]
+
+
+KW = dict(mode="point_major", splits=4)
+
+
+def _alone(spec):
+    import torch
+    from paper_1910_01965_amd import zmc
+    d_axis = zmc.axis_tensor(spec)
+    f = torch.empty(spec.G, dtype=torch.float64, device="cuda")
+    s = torch.empty(spec.G, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    zmc.scan_device(spec, d_axis, f, s, stream=torch.cuda.current_stream(), **KW)
+    torch.cuda.synchronize()
+    return f.cpu().numpy().copy(), s.cpu().numpy().copy()
+
+
+def _outputs(spec, copies):
+    import torch
+    from paper_1910_01965_amd import zmc
+    d_axis = zmc.axis_tensor(spec)
+    outs = [(torch.full((spec.G,), float("nan"), dtype=torch.float64, device="cuda"),
+             torch.full((spec.G,), float("nan"), dtype=torch.float64, device="cuda"))
+            for _ in range(copies)]
+    return d_axis, outs
+
+
+@pytest.mark.parametrize("streams", [1, 2])
+def test_back_to_back_scans_reuse_workspaces(streams):
+    import torch
+    from paper_1910_01965_amd import zmc
+    specs = _specs()
+    print(f"workspace reuse, streams={streams}, {len(specs)} specs", flush=True)
+    sys.stdout.flush()
+    want = [_alone(sp) for sp in specs]
+    rounds = 3
+    bufs = [_outputs(sp, rounds) for sp in specs]
+    ss = [torch.cuda.Stream() for _ in range(streams)]
+    torch.cuda.synchronize()
+    k = 0
+    for r in range(rounds):                 # small to large, then again: buffers retire and return
+        for i, sp in enumerate(specs):
+            d_axis, outs = bufs[i]
+            f, s = outs[r]
+            zmc.scan_device(sp, d_axis, f, s, stream=ss[k % streams], **KW)
+            k += 1
+    torch.cuda.synchronize()
+    for i in range(len(specs)):
+        for r in range(rounds):
+            f, s = bufs[i][1][r]
+            assert np.array_equal(f.cpu().numpy(), want[i][0]), (i, r)
+            assert np.array_equal(s.cpu().numpy(), want[i][1]), (i, r)
