@@ -165,8 +165,13 @@ zmc_status zmc_scan(const zmc_scan_desc* desc, double* f, double* sigma);
 /* Asynchronous scan on `stream` with device-resident data: d_axis_vals holds
  * the concatenated value lists (sum L_l doubles; may be NULL when M = 0);
  * d_f and d_sigma receive G doubles each.  desc->axis_vals is not read.
- * Split partials, when the plan needs them, live in stream-ordered device
- * memory that is released on the same stream.  Returns after enqueueing.
+ * Split partials, when the plan needs them (16 B per point and sample
+ * piece), come from a per-device cache of at most four buffers of up to
+ * 256 MB each, held by the library until the process ends and reused
+ * without a host wait (a buffer still in use by another call's kernels is
+ * ordered after them on the device); larger partials, and every call made
+ * under stream capture, live in stream-ordered device memory released on
+ * the same stream.  Returns after enqueueing.
  * The call may be recorded by stream capture into a caller's HIP graph
  * (kernels plus, for split plans, graph memory nodes; no memset nodes); each
  * replay recomputes the same results, provided the device has been used
