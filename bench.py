@@ -122,6 +122,19 @@ def valu_ops_per_sample(family, N):
     return float(rng + mapping + integrand + 8)
 
 
+def mix_roofline(specs, seconds):
+    """Roofline of a whole mix of scans (a batch, a served trace): every scan's
+    algorithmic lane-operations (valu_ops_per_sample x samples) over the wall
+    time of the mix, against VALU_PEAK."""
+    ops = sum(sp.G * sp.samples * valu_ops_per_sample(sp.family, sp.N) for sp in specs)
+    samples = sum(sp.G * sp.samples for sp in specs)
+    achieved = ops / seconds
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+            "unit": "T lane-op/s", "frac": achieved / VALU_PEAK,
+            "ops_per_sample_mean": ops / samples,
+            "what": "algorithmic lane-operations of every scan in the mix / its wall time"}
+
+
 def grid_1e10_run():
     """The 10^10-point grid (160 GB of f and sigma) streamed to the host as
     twenty ranges of 5e8 points through two reused pinned 4 GB arrays, as a
@@ -233,7 +246,8 @@ def batched_run(reps=1, count=512, seed=3):
             "plain_back_to_back": total / t_plain, "ratio_vs_plain": t_plain / t_batch,
             "scans": len(specs), "samples": total, "tiles": info["tiles"],
             "variants": info["variants"], "graph": bool(info["graph"]),
-            "grid_pts_per_s": sum(sp.G for sp in specs) / t_batch}
+            "grid_pts_per_s": sum(sp.G for sp in specs) / t_batch,
+            "roofline": mix_roofline(specs, t_batch)}
 
 
 def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=0, compare_plain=False,
@@ -277,7 +291,7 @@ def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=0, compare_pl
                          "mean": float(lat.mean()), "max": float(lat.max())},
            "slices": stats["slices"], "bytes_peak": stats["bytes_peak"],
            "budget_bytes": budget, "max_slots": max_slots if max_slots > 0 else 256,
-           "admission": admission,
+           "admission": admission, "roofline": mix_roofline(specs, t_all),
            "server_reported": {k: stats[k] for k in ("latency_p50_s", "latency_p99_s",
                                                      "latency_max_s", "samples_per_s")}}
     if compare_plain:

@@ -34,3 +34,17 @@ def test_serving_window_fits_the_time_budget():
     # less time left: the window halves until the section fits, never below 4 s
     assert bench.fit_serving_window(60.0, 250.0, 7.1e11, 7.1e11, 4.0, trace) == 30.0
     assert bench.fit_serving_window(60.0, 10.0, 7.1e11, 7.1e11, 4.0, trace) == 4.0
+
+
+def test_mix_roofline_weights_each_scan_by_its_samples():
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1910_01965_amd import workloads as wl
+    a = wl.gauss_2p(points_per_axis=10, samples=1024)            # 51 ops per sample
+    b = wl.cosexp_4p(precision="fp32").with_(samples=4096)
+    b = b.with_(axes=[ax[:3] for ax in b.axes])                  # 81 points, 39 ops per sample
+    r = bench.mix_roofline([a, b], 2.0)
+    ops = 100 * 1024 * 51 + 81 * 4096 * 39
+    assert r["bound"] == "alu"
+    assert abs(r["frac"] - ops / 2.0 / bench.VALU_PEAK) < 1e-15
+    assert abs(r["ops_per_sample_mean"] - ops / (100 * 1024 + 81 * 4096)) < 1e-12
