@@ -251,12 +251,15 @@ def batched_run(reps=1, count=512, seed=3):
 
 
 def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=0, compare_plain=False,
-                admission="fifo"):
+                admission="fifo", verify=0):
     """Poisson arrivals of scans shaped like the 512-scan batch (family,
     N, grid size, samples drawn by default_rng(seed); request i has Philox
     seed i) into the continuous-batching server; latency = completion -
     submission.  Optionally the same request trace back to back through
-    the plain entry point."""
+    the plain entry point, and `verify` requests spread evenly over the
+    trace re-run alone, one at a time, in a fresh server: a request's tiles
+    depend only on the request, so each must equal its served result bit
+    for bit.  Every other request is released once it has finished."""
     import torch
     from paper_1910_01965_amd import workloads as wl
     from paper_1910_01965_amd import zmc
@@ -275,9 +278,16 @@ def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=0, compare_pl
             time.sleep(ta - now)
         tickets.append(srv.submit(sp))
     lat = []
+    picked = set(np.linspace(0, n_req - 1, min(verify, n_req)).round().astype(int).tolist()) \
+        if verify > 0 else set()
+    served = {}
     t_say = time.perf_counter()
     for i, t in enumerate(tickets):
         lat.append(srv.wait(t)[1])
+        if i in picked:
+            served[i] = srv.outputs(t)
+        else:
+            srv.release(t)
         if time.perf_counter() - t_say > 15.0:  # progress of long runs
             log(f"  serving: {i + 1}/{n_req} requests done, {time.perf_counter() - t0:.0f} s")
             t_say = time.perf_counter()
@@ -294,6 +304,21 @@ def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=0, compare_pl
            "admission": admission, "roofline": mix_roofline(specs, t_all),
            "server_reported": {k: stats[k] for k in ("latency_p50_s", "latency_p99_s",
                                                      "latency_max_s", "samples_per_s")}}
+    if served:
+        alone = zmc.Server(hbm_budget_bytes=budget, max_slots=max_slots, admission=admission)
+        equal = 0
+        for i in sorted(served):
+            t = alone.submit(specs[i])
+            alone.wait(t)
+            f, s = alone.outputs(t)
+            torch.cuda.synchronize()
+            equal += int(torch.equal(f, served[i][0]) and torch.equal(s, served[i][1]))
+        alone.close()
+        out["alone_rerun"] = {"requests": len(served), "bitwise_equal": equal,
+                              "what": "requests spread evenly over the trace, re-run one at a time "
+                                      "in a fresh server, vs their served f and sigma"}
+        log(f"  re-run alone: {equal}/{len(served)} requests bitwise equal to their served results")
+        del served
     if compare_plain:
         outs = [(torch.empty(sp.G, dtype=torch.float64, device="cuda"),
                  torch.empty(sp.G, dtype=torch.float64, device="cuda")) for sp in specs]
@@ -613,7 +638,7 @@ def serving_section(args, out):
     if seconds != asked:
         log(f"serving: {asked} s of arrivals would not fit the time budget; running {seconds} s")
     log(f"serving: 200 req/s for {seconds} s (arrival order), then the same trace as plain launches")
-    over = serving_run(200.0, seconds, compare_plain=True, max_slots=args.serve_max_slots)
+    over = serving_run(200.0, seconds, compare_plain=True, max_slots=args.serve_max_slots, verify=64)
     over["arrival_seconds_asked"] = asked
     log(f"serving overload: {over['value']:.4g} samples/s ({over['ratio_vs_plain']:.3f}x plain), "
         f"p50 {over['latency_s']['p50']:.3f} s, p99 {over['latency_s']['p99']:.3f} s")
