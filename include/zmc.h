@@ -185,7 +185,8 @@ zmc_status zmc_scan_device(const zmc_scan_desc* desc, const double* d_axis_vals,
  * the decomposition of the whole grid, so the results equal those of one
  * scan of the whole grid bit for bit.  While the device computes chunk i,
  * chunk i-1 is copied back over PCIe and, when f and sigma are pageable,
- * from pinned staging into them on host threads; outputs in pinned memory
+ * from pinned staging into them on host threads ($ZMC_COPY_THREADS, 1..64,
+ * default 8); outputs in pinned memory
  * (hipHostMalloc) take the copies directly.  Device memory: the lists plus
  * 2 x 16 B x chunk_points plus the chunk's split partials.  Synchronous.
  * f and sigma must be host memory (ZMC_E_INVALID for device pointers). */

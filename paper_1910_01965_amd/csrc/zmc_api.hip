@@ -666,6 +666,25 @@ zmc_status zmc_debug_values(const zmc_scan_desc* desc, const double* d_axis_vals
 }
 
 
+}  // extern "C"
+
+namespace {
+
+// Host threads that store a chunk's results from pinned staging into pageable
+// outputs: $ZMC_COPY_THREADS if set (1..64), else 8.
+uint64_t copy_threads() {
+  static const uint64_t n = [] {
+    const char* env = getenv("ZMC_COPY_THREADS");
+    const int v = (env && *env) ? atoi(env) : 0;
+    return (uint64_t)(v >= 1 && v <= 64 ? v : 8);
+  }();
+  return n;
+}
+
+}  // namespace
+
+extern "C" {
+
 zmc_status zmc_scan_chunked(const zmc_scan_desc* desc, double* f, double* sigma,
                             uint64_t chunk_points) {
   uint64_t G = 0;
@@ -742,7 +761,7 @@ zmc_status zmc_scan_range(const zmc_scan_desc* desc, uint64_t g_begin, uint64_t 
   auto host_copy = [&](int slot, uint64_t g0, uint64_t n) {
     // pinned staging -> the caller's arrays, on a few host threads
     const double* src = stage + (size_t)slot * 2 * C;
-    const uint64_t parts = n >= ((uint64_t)1 << 20) ? 4 : 1;
+    const uint64_t parts = n >= ((uint64_t)1 << 20) ? copy_threads() : 1;
     std::vector<std::thread> th;
     for (uint64_t t = 0; t < parts; ++t) {
       const uint64_t a = n * t / parts, b = n * (t + 1) / parts;
