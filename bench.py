@@ -598,15 +598,18 @@ def left(args):
     return args.time_budget - (time.perf_counter() - T_START)
 
 
-def fit_serving_window(asked, left_s, cap, plain, short_s, trace_samples):
+def fit_serving_window(asked, left_s, cap, plain, short_s, trace_samples, steady_s=8.0):
     """The arrival window to run: `asked` seconds, halved (down to 4 s) while
     the serving section would not fit in `left_s` seconds.  Its cost: serving
     the trace (never shorter than its arrivals) at `cap` samples/s, the same
-    trace as plain launches at `plain` samples/s, the two short runs and 30 s
-    of margin."""
+    trace as plain launches at `plain` samples/s, the shortest-first run over
+    `short_s` seconds of the same arrivals, the steady run and 30 s of
+    margin."""
+    short_cost = max(short_s, trace_samples(short_s) / cap)
+
     def cost(sec):
         tot = trace_samples(sec)
-        return max(sec, tot / cap) + tot / plain + 2.5 * short_s + 30.0
+        return max(sec, tot / cap) + tot / plain + short_cost + 1.25 * steady_s + 30.0
 
     seconds = asked
     while seconds > 4.0 and cost(seconds) > left_s:
@@ -634,7 +637,8 @@ def serving_section(args, out):
         return sum(sp.G * sp.samples for sp in wl.batched_512(count=k, seed=7))
 
     asked = seconds
-    seconds = fit_serving_window(asked, left(args), cap, plain, short_s, trace_samples)
+    seconds = fit_serving_window(asked, left(args), cap, plain, short_s, trace_samples,
+                                 args.serve_steady_seconds)
     if seconds != asked:
         log(f"serving: {asked} s of arrivals would not fit the time budget; running {seconds} s")
     log(f"serving: 200 req/s for {seconds} s (arrival order), then the same trace as plain launches")
@@ -643,14 +647,16 @@ def serving_section(args, out):
     log(f"serving overload: {over['value']:.4g} samples/s ({over['ratio_vs_plain']:.3f}x plain), "
         f"p50 {over['latency_s']['p50']:.3f} s, p99 {over['latency_s']['p99']:.3f} s")
     log(f"serving: 200 req/s for {short_s} s, shortest first")
-    short = serving_run(200.0, short_s, admission="shortest", max_slots=args.serve_max_slots)
+    short = serving_run(200.0, short_s, admission="shortest", max_slots=args.serve_max_slots,
+                        verify=16)
     short["ratio_vs_plain"] = short["value"] / over["plain_back_to_back"]
     log(f"serving overload, shortest first: {short['value']:.4g} samples/s, "
         f"p50 {short['latency_s']['p50']:.3f} s, p99 {short['latency_s']['p99']:.3f} s")
     mean_req = over["samples"] / max(1, over["requests"])
     steady_rate = 0.7 * cap / mean_req
-    log(f"serving steady: {steady_rate:.1f} req/s for {2 * short_s} s")
-    steady = serving_run(steady_rate, 2 * short_s, seed=8, max_slots=args.serve_max_slots)
+    log(f"serving steady: {steady_rate:.1f} req/s for {args.serve_steady_seconds} s")
+    steady = serving_run(steady_rate, args.serve_steady_seconds, seed=8,
+                         max_slots=args.serve_max_slots)
     slots = args.serve_max_slots if args.serve_max_slots > 0 else 256
     return {"overload_200_per_s": over, "overload_200_per_s_shortest_first": short,
             "steady_0p7_capacity": steady,
@@ -677,7 +683,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="arrival window of the specified serving run (arrival order)")
     ap.add_argument("--serve-short-seconds", type=float, default=4.0,
-                    help="arrival window of the shortest-first run (twice it for the steady run)")
+                    help="arrival window of the shortest-first run (at most --serve-seconds)")
+    ap.add_argument("--serve-steady-seconds", type=float, default=8.0,
+                    help="arrival window of the steady run at 0.7x capacity")
     ap.add_argument("--serve-max-slots", type=int, default=0,
                     help="admitted requests at once (0 = the server's default, 256)")
     ap.add_argument("--time-budget", type=float, default=540.0,

@@ -48,3 +48,15 @@ def test_mix_roofline_weights_each_scan_by_its_samples():
     assert r["bound"] == "alu"
     assert abs(r["frac"] - ops / 2.0 / bench.VALU_PEAK) < 1e-15
     assert abs(r["ops_per_sample_mean"] - ops / (100 * 1024 + 81 * 4096)) < 1e-12
+
+
+def test_serving_window_counts_a_long_shortest_first_run():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    def trace(sec):
+        return 1.72e12 * sec
+
+    # a 60 s shortest-first run costs another ~145 s: 60 s no longer fits 470 s
+    assert bench.fit_serving_window(60.0, 470.0, 7.1e11, 7.1e11, 60.0, trace) == 30.0
+    assert bench.fit_serving_window(60.0, 900.0, 7.1e11, 7.1e11, 60.0, trace) == 60.0
