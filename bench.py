@@ -504,24 +504,28 @@ USER_GAUSS = ("template <typename T> __device__ T integrand(const T* y, const T*
 
 def user_run(spec, out):
     """The Gaussian bench workload as a run-time-compiled user integrand (the
-    integrand written plainly, as a user would), FP32 and FP64, beside the
-    compiled-in family; plus the one-time compile and load cost."""
+    integrand written plainly, as a user would), FP32, FP64 and FP32 with
+    approximate transcendentals, beside the compiled-in family; plus the
+    one-time compile and load cost."""
     import torch
     from paper_1910_01965_amd import zmc
     res = {"source": USER_GAUSS}
-    for prec, steps, ref in (("fp32", 5, out["value"]), ("fp64", 2, out["fp64"]["value"])):
-        sp = spec.with_(family="user", source=USER_GAUSS, precision=prec, name=spec.name + "_user")
+    for key, prec, fast, steps, ref in (("fp32", "fp32", False, 5, out["value"]),
+                                        ("fp64", "fp64", False, 2, out["fp64"]["value"]),
+                                        ("fp32_fast_math", "fp32", True, 5, out["value"])):
+        sp = spec.with_(family="user", source=USER_GAUSS, precision=prec, name=spec.name + "_user",
+                        fast_math=fast)
         t0 = time.perf_counter()
-        zmc.integrand(USER_GAUSS)
+        zmc.integrand(USER_GAUSS, fast)
         f, s = zmc.scan(sp.with_(axes=[a[:2] for a in sp.axes], samples=64))  # compiles (prec, N, M)
         torch.cuda.synchronize()
         first = time.perf_counter() - t0
-        log(f"config user gauss {prec}: first use (compile + load) {first:.2f} s, {steps} steps")
+        log(f"config user gauss {key}: first use (compile + load) {first:.2f} s, {steps} steps")
         r = time_path(sp, steps, 1)
         ms = r["wall_s"] * 1e3 / steps
         v = sp.G * sp.samples / (ms / 1e3)
-        res[prec] = {"samples_per_s": v, "ms_per_step": ms, "kernel_ms": float(np.mean(r["kernel_ms"])),
-                     "vs_compiled_family": v / ref, "first_use_s": first}
+        res[key] = {"samples_per_s": v, "ms_per_step": ms, "kernel_ms": float(np.mean(r["kernel_ms"])),
+                    "vs_compiled_family": v / ref, "first_use_s": first}
         log(f"  {v:.4g} samples/s ({v / ref:.3f}x the compiled-in family)")
     return res
 

@@ -295,6 +295,22 @@ zmc_status zmc_debug_values(const zmc_scan_desc* desc, const double* d_axis_vals
  * handle must outlive every batch and request that uses it. */
 zmc_status zmc_integrand_create(const char* source, zmc_integrand** out);
 
+/* zmc_integrand_create with option flags (0 = zmc_integrand_create).
+ * ZMC_INTEGRAND_FAST_MATH: the handle's FP32 variants are compiled with
+ * approximate transcendentals (clang's -fgpu-approx-transcendentals and
+ * -fapprox-func): expf, exp2f, logf, log2f, sinf, cosf and the like map to
+ * the hardware's approximate instructions (v_exp_f32, v_log_f32, v_sin_f32,
+ * v_cos_f32 with a scaling), and FP32 division and square root may use
+ * approximations of about an ulp.  Relative error per call is then a few
+ * FP32 ulps, except that sinf and cosf lose accuracy linearly in |x|
+ * (about 1e-4 absolute at |x| = 1000: no exact argument reduction).  For
+ * callers whose FP32 integrands call such functions with moderate
+ * arguments and who want the compiled-in families' speed.  FP64 variants
+ * are compiled exactly as without the flag, so their results do not change.
+ * Unknown flag bits give ZMC_E_INVALID. */
+#define ZMC_INTEGRAND_FAST_MATH 1u
+zmc_status zmc_integrand_create_ex(const char* source, uint32_t flags, zmc_integrand** out);
+
 /* Compiler log of the handle's last build (empty when it produced none). */
 const char* zmc_integrand_log(const zmc_integrand* integrand);
 

@@ -44,6 +44,8 @@ class ScanSpec:
     # integrand<T>(y, x, p), see include/zmc.h) and its constants p
     source: str = ""
     params: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    # family "user": FP32 variants with approximate transcendentals
+    fast_math: bool = False
 
     def __post_init__(self):
         self.axes = [np.ascontiguousarray(a, dtype=np.float64).ravel() for a in self.axes]
@@ -73,7 +75,8 @@ class ScanSpec:
     def with_(self, **kw):
         d = dict(family=self.family, axes=self.axes, lo=self.lo, hi=self.hi,
                  samples=self.samples, seed=self.seed, precision=self.precision,
-                 name=self.name, meta=dict(self.meta), source=self.source, params=self.params)
+                 name=self.name, meta=dict(self.meta), source=self.source, params=self.params,
+                 fast_math=self.fast_math)
         d.update(kw)
         return ScanSpec(**d)
 

@@ -28,7 +28,7 @@ EXPORTS = ("zmc_last_error", "zmc_version", "zmc_validate", "zmc_plan", "zmc_sca
            "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch", "zmc_tune_source",
            "zmc_server_create", "zmc_server_submit", "zmc_server_poll", "zmc_server_wait",
            "zmc_server_get_stats", "zmc_server_release", "zmc_server_destroy",
-           "zmc_integrand_create",
+           "zmc_integrand_create", "zmc_integrand_create_ex",
            "zmc_integrand_log", "zmc_integrand_destroy", "zmc_scan_chunked", "zmc_scan_range",
            "zmc_debug_valu_probe", "zmc_debug_rate_probe")
 
@@ -157,10 +157,12 @@ def load():
         lib.zmc_server_release.argtypes = [vp, ctypes.c_uint64]
         lib.zmc_server_destroy.argtypes = [vp]
         lib.zmc_integrand_create.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+        lib.zmc_integrand_create_ex.argtypes = [ctypes.c_char_p, ctypes.c_uint32, ctypes.POINTER(vp)]
         lib.zmc_integrand_log.argtypes = [vp]
         lib.zmc_integrand_log.restype = ctypes.c_char_p
         lib.zmc_integrand_destroy.argtypes = [vp]
-        for name in ("zmc_integrand_create", "zmc_integrand_destroy", "zmc_scan_chunked",
+        for name in ("zmc_integrand_create", "zmc_integrand_create_ex", "zmc_integrand_destroy",
+                     "zmc_scan_chunked",
                      "zmc_scan_range",
                      "zmc_validate", "zmc_plan", "zmc_scan", "zmc_scan_device",
                      "zmc_scan_device_ex", "zmc_scan_device_noalloc", "zmc_debug_words", "zmc_debug_values",
@@ -179,17 +181,23 @@ def _check(status):
         raise ZmcError(status, load().zmc_last_error().decode())
 
 
-class Integrand:
-    """A user integrand compiled at run time (zmc_integrand_create): `source`
-    defines template <typename T> __device__ T integrand(const T* y,
-    const T* x, const T* p).  Raises ZmcError (with the compiler's log) when
-    it does not compile."""
+INTEGRAND_FAST_MATH = 1
 
-    def __init__(self, source):
+
+class Integrand:
+    """A user integrand compiled at run time (zmc_integrand_create_ex): `source`
+    defines template <typename T> __device__ T integrand(const T* y,
+    const T* x, const T* p).  `fast_math`: FP32 variants use approximate
+    transcendentals (ZMC_INTEGRAND_FAST_MATH).  Raises ZmcError (with the
+    compiler's log) when it does not compile."""
+
+    def __init__(self, source, fast_math=False):
         lib = load()
         h = ctypes.c_void_p()
-        _check(lib.zmc_integrand_create(source.encode(), ctypes.byref(h)))
+        flags = INTEGRAND_FAST_MATH if fast_math else 0
+        _check(lib.zmc_integrand_create_ex(source.encode(), ctypes.c_uint32(flags), ctypes.byref(h)))
         self.source = source
+        self.fast_math = bool(fast_math)
         self.handle = h.value
         self._lib = lib
 
@@ -212,15 +220,17 @@ _integrands = {}
 _integrands_lock = threading.Lock()
 
 
-def integrand(source):
-    """The process-wide Integrand for `source` (compiled once, kept for the
-    life of the process, so its kernels are never unloaded under a scan)."""
+def integrand(source, fast_math=False):
+    """The process-wide Integrand for (`source`, `fast_math`) (compiled once,
+    kept for the life of the process, so its kernels are never unloaded under
+    a scan)."""
     if not source:
         raise ZmcError(1, "family 'user' needs ScanSpec.source")
+    key = (source, bool(fast_math))
     with _integrands_lock:
-        it = _integrands.get(source)
+        it = _integrands.get(key)
         if it is None:
-            it = _integrands[source] = Integrand(source)
+            it = _integrands[key] = Integrand(source, fast_math)
     return it
 
 
@@ -235,7 +245,8 @@ class Desc:
         self.hi = np.ascontiguousarray(spec.hi, dtype=np.float64)
         prec = precision or spec.precision
         self.params = np.ascontiguousarray(getattr(spec, "params", np.zeros(0)), dtype=np.float64)
-        self.integrand = integrand(spec.source) if spec.family == "user" else None
+        self.integrand = integrand(spec.source, getattr(spec, "fast_math", False)) \
+            if spec.family == "user" else None
         self.c = ScanDesc(
             M=len(spec.axes), N=len(self.lo),
             axis_len=self.axis_len.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),

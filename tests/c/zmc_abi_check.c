@@ -249,6 +249,18 @@ int main(int argc, char** argv) {
   expect(zmc_oracle_scan(&o, NULL, G_ALL, fr, sr) == 0, "oracle scan, user function");
   expect(zmc_scan(&d, f, s) == ZMC_OK, "zmc_scan, user integrand FP64");
   compare("user integrand FP64 vs oracle", f, s, fr, sr, G_ALL, (double)d.samples, 1e-12, 1e-12);
+  /* the same function with approximate FP32 transcendentals */
+  zmc_integrand* hf = NULL;
+  expect(zmc_integrand_create_ex(kSource, 2u, &hf) == ZMC_E_INVALID && hf == NULL,
+         "zmc_integrand_create_ex refuses unknown flags");
+  expect(zmc_integrand_create_ex(kSource, ZMC_INTEGRAND_FAST_MATH, &hf) == ZMC_OK && hf != NULL,
+         "zmc_integrand_create_ex, fast math");
+  d.integrand = hf;
+  d.precision = ZMC_FP32_MERGE64;
+  expect(zmc_scan(&d, f, s) == ZMC_OK, "zmc_scan, fast-math user integrand FP32");
+  compare("fast-math user integrand FP32 vs oracle", f, s, fr, sr, G_ALL, (double)d.samples, 2e-5,
+          1e-3);
+  expect(zmc_integrand_destroy(hf) == ZMC_OK, "zmc_integrand_destroy (fast math)");
   expect(zmc_integrand_destroy(h) == ZMC_OK, "zmc_integrand_destroy");
   device_checks(vals, len);
   printf("%s\n", failures ? "FAILED" : "passed");

@@ -351,3 +351,15 @@ def test_wide_scans_take_at_most_256_threads_per_block(lib):
     assert ei.value.status == 1 and "256" in str(ei.value)
     assert zmc.plan(sp, mode="sample_major", block=256, cu_count=256)["block"] == 256
     assert zmc.plan(GOOD, mode="sample_major", block=1024, cu_count=256)["block"] == 1024
+
+
+def test_fast_math_integrand_compiles_without_a_gpu(lib):
+    it = zmc.Integrand(USER_SRC, fast_math=True)   # compiles an FP64 and an FP32 variant
+    assert it.handle and it.fast_math
+    it.close()
+    h = ctypes.c_void_p()
+    assert lib.zmc_integrand_create_ex(USER_SRC.encode(), ctypes.c_uint32(2), ctypes.byref(h)) == 1
+    assert "unknown flags" in lib.zmc_last_error().decode() and not h.value
+    # process-wide handles are per (source, mode)
+    assert zmc.integrand(USER_SRC) is not zmc.integrand(USER_SRC, fast_math=True)
+    assert zmc.integrand(USER_SRC, fast_math=True) is zmc.integrand(USER_SRC, fast_math=True)

@@ -98,6 +98,39 @@ def test_user_values_match_oracle(precision):
                 assert np.all(np.abs(got - ref) <= 2e-5 * (1.0 + np.abs(ref))), (spec.name, g)
 
 
+def test_fast_math_integrands():
+    """ZMC_INTEGRAND_FAST_MATH: FP32 scans with approximate transcendentals and
+    division meet the FP32 bar against the oracle in both layouts; the same
+    handle's FP64 variants equal the accurate handle's bit for bit; and the
+    FP32 results differ from the accurate handle's (the flag reaches the
+    compiler)."""
+    import torch
+    zmc = _zmc()
+    cases = [c for c in _cases("fp32") if c.name in ("wave N3", "peak N3 M3", "product N4 G300")]
+    assert len(cases) == 3
+    differ = 0
+    for spec in cases:
+        fast = spec.with_(fast_math=True)
+        f_ref, s_ref = zo.scan(spec)
+        for mode in ("point_major", "sample_major"):
+            _say(f"fast-math user {spec.name} fp32 {mode}")
+            f, s = zmc.scan(fast, mode=mode)
+            fa, _ = zmc.scan(spec, mode=mode)
+            torch.cuda.synchronize()
+            f, s, fa = f.cpu().numpy(), s.cpu().numpy(), fa.cpu().numpy()
+            _, _, msg = parity.check(f, s, f_ref, s_ref, spec.samples, "fp32", spec.name + " fast",
+                                     small_n=spec.samples < 4096,
+                                     volume=float(np.prod(spec.hi - spec.lo)))
+            _say(msg)
+            differ += int(not np.array_equal(f, fa))
+        _say(f"fast-math user {spec.name} fp64")
+        f64, s64 = zmc.scan(fast.with_(precision="fp64"))
+        f64a, s64a = zmc.scan(spec.with_(precision="fp64"))
+        torch.cuda.synchronize()
+        assert torch.equal(f64, f64a) and torch.equal(s64, s64a), spec.name
+    assert differ > 0
+
+
 def test_user_splits_and_repeat_bitwise():
     import torch
     zmc = _zmc()
@@ -266,16 +299,17 @@ def test_a_variant_that_fails_to_compile_fails_alone():
     parity.check(f.cpu().numpy(), s.cpu().numpy(), f_ref, s_ref, ok64.samples, "fp64", "after failures")
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_user_gaussian_at_the_benchmark_size(precision):
+@pytest.mark.parametrize("precision,fast_math", [("fp32", False), ("fp64", False), ("fp32", True)])
+def test_user_gaussian_at_the_benchmark_size(precision, fast_math):
     """The Gaussian written as a user integrand on the full 1000 x 1000 grid
-    with 2^14 samples, the configuration the benchmark times: 300 sampled
-    points and both corners against the oracle."""
+    with 2^14 samples, the configuration the benchmark times (FP32 also with
+    approximate transcendentals): 300 sampled points and both corners against
+    the oracle."""
     import torch
     zmc = _zmc()
     src = HEAD + "  return exp(-(x[0] * y[0] * y[0] + x[1] * y[1] * y[1] + y[2] * y[2]));\n}\n"
-    spec = wl.gauss_2p(precision=precision).with_(family="user", source=src)
-    _say(f"user gaussian 1e6 points {precision}")
+    spec = wl.gauss_2p(precision=precision).with_(family="user", source=src, fast_math=fast_math)
+    _say(f"user gaussian 1e6 points {precision} fast_math={fast_math}")
     f, s = zmc.scan(spec)
     torch.cuda.synchronize()
     idx = np.sort(np.random.default_rng(2).choice(spec.G, 300, replace=False))
