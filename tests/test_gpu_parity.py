@@ -287,6 +287,11 @@ EDGE = [
     wl.ScanSpec("sin_sum", [np.array([0.0, 0.5 + k / 16.0]) for k in range(16)], np.zeros(8),
                 np.ones(8), 33, 10),
     wl.ScanSpec("gauss", [np.linspace(0.1, 9, 3)] * 8, np.zeros(8), np.ones(8), 257, 11),
+    # the descriptor's limits together: M = 16 axes and N = 16 dimensions
+    wl.ScanSpec("sin_sum", [np.array([0.0, 0.25 + k / 32.0]) for k in range(16)], -np.ones(16),
+                np.linspace(0.5, 1.0, 16), 33, 12),
+    wl.ScanSpec("gauss", [np.array([0.2, 1.0 + k / 8.0]) for k in range(16)], np.zeros(16),
+                np.ones(16), 17, 13),
 ]
 
 
