@@ -246,6 +246,7 @@ def batched_run(reps=1, count=512, seed=3):
             "plain_back_to_back": total / t_plain, "ratio_vs_plain": t_plain / t_batch,
             "scans": len(specs), "samples": total, "tiles": info["tiles"],
             "variants": info["variants"], "graph": bool(info["graph"]),
+            "shape_seed": seed, "philox_seeds": f"0..{len(specs) - 1} (scan i has seed i)",
             "grid_pts_per_s": sum(sp.G for sp in specs) / t_batch,
             "roofline": mix_roofline(specs, t_batch)}
 
@@ -296,6 +297,7 @@ def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=0, compare_pl
     stats = srv.stats()
     srv.close()
     out = {"rate_per_s": rate, "arrival_seconds": duration, "requests": n_req, "samples": total,
+           "arrival_and_shape_seed": seed, "philox_seeds": "request i has seed i",
            "value": total / t_all, "unit": "samples/s", "wall_seconds": t_all,
            "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                          "mean": float(lat.mean()), "max": float(lat.max())},
@@ -401,7 +403,8 @@ def cpu_baseline_others(seed=0):
     dt = time.perf_counter() - t0
     n = len(idx) * sp.samples
     out["cosexp_4p_1e8pts_n4096"] = {
-        "sample": f"the {len(idx)}-point seeded subsample", "samples": n, "seconds": dt,
+        "sample": f"the {len(idx)}-point subsample: np.random.default_rng(42).choice(10**8, "
+                  f"10**4, replace=False), sorted", "samples": n, "seconds": dt,
         "samples_per_s": n / dt, "full_grid_one_core_s_extrapolated": sp.G * sp.samples / (n / dt)}
     rng = np.random.default_rng(seed)
     t_sum = t_full = 0.0
@@ -783,7 +786,8 @@ def main():
             c = out["configs"][name] = {
                 "samples_per_s": sp.G * sp.samples / (ms / 1e3), "grid_pts_per_s": sp.G / (ms / 1e3),
                 "ms_per_step": ms, "ms_per_step_with_events": r["wall_s"] * 1e3 / steps,
-                "kernel_ms": km, "finite": w["finite"] and r["finite"], "plan": r["plan"],
+                "kernel_ms": km, "finite": w["finite"] and r["finite"], "seed": sp.seed,
+                "plan": r["plan"],
                 "kernel_ms_median": float(np.median(r["kernel_ms"])),
                 "kernel_ms_min": float(np.min(r["kernel_ms"])), "steps": steps}
             if kern:

@@ -371,7 +371,8 @@ hipError_t ws_acquire(int dev, size_t bytes, hipStream_t s, Workspace* out) {
     if (out->used && hipEventQuery(out->done) != hipSuccess) return hipStreamWaitEvent(s, out->done, 0);
     return hipSuccess;
   }
-  if (drop.ptr != nullptr) {  // hipFree waits for the device work that may still use it
+  if (drop.ptr != nullptr) {  // the retired buffer's last kernel must finish first
+    if (drop.used) (void)hipEventSynchronize(drop.done);
     (void)hipEventDestroy(drop.done);
     (void)hipFree(drop.ptr);
   }
