@@ -163,8 +163,12 @@ zmc_status zmc_plan(const zmc_scan_desc* desc, const zmc_launch_opts* opts,
 zmc_status zmc_scan(const zmc_scan_desc* desc, double* f, double* sigma);
 
 /* Asynchronous scan on `stream` with device-resident data: d_axis_vals holds
- * the concatenated value lists (sum L_l doubles; may be NULL when M = 0);
- * d_f and d_sigma receive G doubles each.  desc->axis_vals is not read.
+ * the concatenated value lists (sum L_l doubles); d_f and d_sigma receive G
+ * doubles each.  desc->axis_vals is read only when d_axis_vals is NULL (and
+ * M > 0): the call then stages the lists itself into a device copy that it
+ * frees on the stream, and has read desc->axis_vals when it returns; under
+ * stream capture that gives ZMC_E_INVALID (a replay cannot re-read host
+ * memory), and with both pointers NULL too.
  * Split partials, when the plan needs them (16 B per point and sample
  * piece), come from a per-device cache of at most four buffers of up to
  * 256 MB each, held by the library until the process ends and reused

@@ -445,8 +445,16 @@ zmc_status zmc_scan_device_ex(const zmc_scan_desc* desc, const double* d_axis_va
   uint64_t G = 0;
   zmc_status st = validate(desc, &G);
   if (st != ZMC_OK) return st;
-  if (desc->M > 0 && d_axis_vals == nullptr) return fail(ZMC_E_INVALID, "d_axis_vals is NULL with M > 0");
+  const bool stage = desc->M > 0 && d_axis_vals == nullptr;  // lists from desc->axis_vals
+  if (stage && desc->axis_vals == nullptr)
+    return fail(ZMC_E_INVALID, "d_axis_vals and desc->axis_vals are both NULL with M > 0");
   if (d_f == nullptr || d_sigma == nullptr) return fail(ZMC_E_INVALID, "d_f or d_sigma is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+  ZMC_HIP(hipStreamIsCapturing(s, &capture));
+  if (stage && capture != hipStreamCaptureStatusNone)
+    return fail(ZMC_E_INVALID, "under stream capture the lists must already be on the device "
+                               "(d_axis_vals): a replay cannot re-read the caller's host memory");
   zmc::Plan pl;
   st = make_plan(desc, G, opts, &pl);
   if (st != ZMC_OK) return st;
@@ -455,32 +463,47 @@ zmc_status zmc_scan_device_ex(const zmc_scan_desc* desc, const double* d_axis_va
     st = zmc::user_kernels(desc->integrand, desc->precision, desc->N, desc->M, &uk);
     if (st != ZMC_OK) return st;
   }
+  int dev = 0, stream_dev = 0;
+  ZMC_HIP(hipGetDevice(&dev));
+  ZMC_HIP(hipStreamGetDevice(s, &stream_dev));
+  const bool use_cache = pl.workspace_bytes > 0 && capture == hipStreamCaptureStatusNone &&
+                         pl.workspace_bytes <= kMaxCachedWorkspace && dev == stream_dev &&
+                         dev >= 0 && dev < kMaxWsDevices;
+
+  // device memory of this call; every path below releases what it took
+  double* staged = nullptr;  // the lists, when the caller passed none (freed on the stream)
+  void* ws = nullptr;        // stream-ordered split partials
+  Workspace cached;          // or split partials from the per-device cache
+  hipError_t e = hipSuccess;
+  if (stage) {
+    uint64_t total = 0;
+    for (int l = 0; l < desc->M; ++l) total += (uint64_t)desc->axis_len[l];
+    e = hipMallocAsync((void**)&staged, 8 * total, s);
+    // from pageable memory the copy has read the caller's lists when it returns
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(staged, desc->axis_vals, 8 * total, hipMemcpyHostToDevice, s);
+    d_axis_vals = staged;
+  }
   zmc::ScanParams p;
   fill_params(desc, G, pl, d_axis_vals, d_f, d_sigma, &p);
-  hipStream_t s = (hipStream_t)stream;
-  void* ws = nullptr;       // stream-ordered workspace
-  Workspace cached;         // or one from the per-device cache
-  int dev = 0;
-  if (pl.workspace_bytes > 0) {
-    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
-    ZMC_HIP(hipStreamIsCapturing(s, &capture));
-    int stream_dev = 0;
-    ZMC_HIP(hipGetDevice(&dev));
-    ZMC_HIP(hipStreamGetDevice(s, &stream_dev));
-    if (capture == hipStreamCaptureStatusNone && pl.workspace_bytes <= kMaxCachedWorkspace &&
-        dev == stream_dev && dev >= 0 && dev < kMaxWsDevices) {
-      ZMC_HIP(ws_acquire(dev, pl.workspace_bytes, s, &cached));
+  if (e == hipSuccess && pl.workspace_bytes > 0) {
+    if (use_cache) {
+      e = ws_acquire(dev, pl.workspace_bytes, s, &cached);
       p.part_mean = (double*)cached.ptr;
     } else {
-      ZMC_HIP(hipMallocAsync(&ws, pl.workspace_bytes, s));
+      e = hipMallocAsync(&ws, pl.workspace_bytes, s);
       p.part_mean = (double*)ws;
     }
     p.part_m2 = p.part_mean + (uint64_t)pl.splits * G;
   }
-  hipEvent_t ev_b = opts ? (hipEvent_t)opts->ev_begin : nullptr;
-  hipEvent_t ev_e = opts ? (hipEvent_t)opts->ev_end : nullptr;
-  hipError_t e = desc->family == ZMC_USER ? zmc::launch_user_scan(uk, p, pl, s, ev_b, ev_e)
-                                           : zmc::launch_scan(p, pl, desc->precision, s, ev_b, ev_e);
+  const char* what = "allocating or staging device memory";
+  if (e == hipSuccess) {
+    what = "scan launch";
+    hipEvent_t ev_b = opts ? (hipEvent_t)opts->ev_begin : nullptr;
+    hipEvent_t ev_e = opts ? (hipEvent_t)opts->ev_end : nullptr;
+    e = desc->family == ZMC_USER ? zmc::launch_user_scan(uk, p, pl, s, ev_b, ev_e)
+                                 : zmc::launch_scan(p, pl, desc->precision, s, ev_b, ev_e);
+  }
   if (ws != nullptr) {
     hipError_t e2 = hipFreeAsync(ws, s);
     if (e == hipSuccess) e = e2;
@@ -489,7 +512,13 @@ zmc_status zmc_scan_device_ex(const zmc_scan_desc* desc, const double* d_axis_va
     hipError_t e2 = ws_release(dev, cached, s);
     if (e == hipSuccess) e = e2;
   }
-  if (e != hipSuccess) return fail(ZMC_E_DEVICE, "scan launch failed: %s", hipGetErrorString(e));
+  if (staged != nullptr) {
+    hipError_t e2 = hipFreeAsync(staged, s);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? ZMC_E_NOMEM : ZMC_E_DEVICE, "%s failed: %s", what,
+                hipGetErrorString(e));
   return ok();
 }
 

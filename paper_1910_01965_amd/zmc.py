@@ -307,12 +307,12 @@ def axis_tensor(spec, device="cuda"):
 def scan_device(spec, d_axis, f, sigma, stream=None, mode=None, block=None, splits=None,
                 events=None):
     """Enqueue the scan of `spec` on `stream`; f and sigma are float64 device
-    tensors of G elements; d_axis holds the parameter lists on the device.
-    `events` = (begin, end) raw hipEvent_t handles recorded around the main
-    kernel."""
+    tensors of G elements; d_axis holds the parameter lists on the device
+    (None: the library stages them from the spec for this call).  `events` =
+    (begin, end) raw hipEvent_t handles recorded around the main kernel."""
     o = _opts(mode, block, splits, events=events)
     d = Desc(spec)
-    _check(load().zmc_scan_device_ex(d.ref, ctypes.c_void_p(d_axis.data_ptr()),
+    _check(load().zmc_scan_device_ex(d.ref, ctypes.c_void_p(d_axis.data_ptr() if d_axis is not None else None),
                                      ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(sigma.data_ptr()),
                                      ctypes.byref(o) if o else None, _stream_ptr(stream)))
 

@@ -81,6 +81,11 @@ def test_null_descriptor_and_outputs(lib):
     d = zmc.Desc(GOOD)
     assert lib.zmc_scan(d.ref, None, None) == 1
     assert lib.zmc_scan_device(d.ref, None, None, None, None) == 1
+    # no device lists and no host lists either, with M > 0
+    d.c.axis_vals = None
+    fake = ctypes.c_void_p(0x1000)                  # never dereferenced: refused first
+    assert lib.zmc_scan_device(d.ref, None, fake, fake, None) == 1
+    assert "both NULL" in lib.zmc_last_error().decode()
     assert lib.zmc_debug_words(0, 0, 0, -1, None, None) == 1
     assert lib.zmc_debug_words(0, 0, 0, 4, None, None) == 1
 

@@ -52,3 +52,34 @@ def test_scan_captured_in_a_graph(splits):
         assert np.array_equal(s.cpu().numpy(), s_eager), rep
         del junk
     g.reset()
+
+
+def test_capture_refuses_lists_left_in_host_memory():
+    """Under capture the parameter lists must already be on the device: a call
+    that would stage them from host memory is refused before it records
+    anything, and the capture goes on."""
+    import torch
+    from paper_1910_01965_amd import zmc
+    spec = wl.gauss_2p(points_per_axis=100, samples=1029, precision="fp32")
+    print("capture with host lists", flush=True)
+    sys.stdout.flush()
+    d_axis = zmc.axis_tensor(spec)
+    f = torch.empty(spec.G, dtype=torch.float64, device="cuda")
+    s = torch.empty(spec.G, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        zmc.scan_device(spec, d_axis, f, s, stream=side)   # warm-up outside the capture
+    torch.cuda.synchronize()
+    f_eager = f.cpu().numpy().copy()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        with pytest.raises(zmc.ZmcError) as ei:
+            zmc.scan_device(spec, None, f, s, stream=torch.cuda.current_stream())
+        zmc.scan_device(spec, d_axis, f, s, stream=torch.cuda.current_stream())
+    assert ei.value.status == 1 and "capture" in str(ei.value)
+    f.fill_(float("nan"))
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(f.cpu().numpy(), f_eager)
+    g.reset()

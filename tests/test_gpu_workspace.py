@@ -79,3 +79,26 @@ def test_back_to_back_scans_reuse_workspaces(streams):
             f, s = bufs[i][1][r]
             assert np.array_equal(f.cpu().numpy(), want[i][0]), (i, r)
             assert np.array_equal(s.cpu().numpy(), want[i][1]), (i, r)
+
+
+@pytest.mark.parametrize("splits", [1, 4])
+def test_lists_staged_by_the_call(splits):
+    """zmc_scan_device with d_axis_vals = NULL stages desc->axis_vals itself:
+    back-to-back calls give the results of the call with device lists, bit
+    for bit."""
+    import torch
+    from paper_1910_01965_amd import zmc
+    spec = wl.gauss_2p(points_per_axis=150, samples=4099, precision="fp32")
+    print(f"lists staged by the call, splits={splits}", flush=True)
+    kw = dict(mode="point_major", splits=splits)
+    d_axis = zmc.axis_tensor(spec)
+    f0 = torch.empty(spec.G, dtype=torch.float64, device="cuda")
+    s0 = torch.empty_like(f0)
+    torch.cuda.synchronize()
+    zmc.scan_device(spec, d_axis, f0, s0, stream=torch.cuda.current_stream(), **kw)
+    outs = [(torch.full_like(f0, float("nan")), torch.full_like(s0, float("nan"))) for _ in range(3)]
+    for f, s in outs:
+        zmc.scan_device(spec, None, f, s, stream=torch.cuda.current_stream(), **kw)
+    torch.cuda.synchronize()
+    for f, s in outs:
+        assert torch.equal(f, f0) and torch.equal(s, s0)
