@@ -372,10 +372,12 @@ hipError_t ws_acquire(int dev, size_t bytes, hipStream_t s, Workspace* out) {
     return hipSuccess;
   }
   if (drop.ptr != nullptr) {  // the retired buffer's last kernel must finish first
+    zmc::log(2, "workspace: retiring a %zu-byte buffer on device %d", drop.bytes, dev);
     if (drop.used) (void)hipEventSynchronize(drop.done);
     (void)hipEventDestroy(drop.done);
     (void)hipFree(drop.ptr);
   }
+  zmc::log(2, "workspace: new %zu-byte buffer on device %d", bytes, dev);
   Workspace w;
   w.bytes = bytes;
   hipError_t e = hipMalloc(&w.ptr, bytes);

@@ -102,3 +102,23 @@ def test_lists_staged_by_the_call(splits):
     torch.cuda.synchronize()
     for f, s in outs:
         assert torch.equal(f, f0) and torch.equal(s, s0)
+
+
+def test_workspace_allocations_are_logged():
+    """ZMC_LOG=2 reports each workspace buffer the cache allocates (a child
+    process, since the library reads the level once)."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import torch\n"
+            "from paper_1910_01965_amd import zmc, workloads as wl\n"
+            "spec = wl.gauss_2p(points_per_axis=100, samples=4099)\n"
+            "for _ in range(3):\n"
+            "    zmc.scan(spec, mode='point_major', splits=4)\n"
+            "torch.cuda.synchronize()\n")
+    print("workspace logging in a child process", flush=True)
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=dict(os.environ, ZMC_LOG="2"),
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stderr.splitlines() if ln.startswith("[zmc] workspace: new")]
+    assert len(lines) == 1, r.stderr[-2000:]        # the three scans share one buffer
