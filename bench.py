@@ -382,6 +382,23 @@ def cpu_baseline_threads(spec, points, seed=0):
             "sample": f"the same {points} points on {threads} threads"}
 
 
+def cpu_full_grid_threads(spec):
+    """The oracle over the whole grid on the host's cores (slices of points
+    from a pool of threads, as cpu_baseline_threads): measured, not
+    extrapolated."""
+    import concurrent.futures as cfut
+    from oracle import oracle as zo
+    threads = max(1, min(16, os.cpu_count() or 1))
+    parts = np.array_split(np.arange(spec.G, dtype=np.uint64), 64 * threads)
+    sp = spec.with_(precision="fp64")
+    t0 = time.perf_counter()
+    with cfut.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda part: zo.scan(sp, part), parts))
+    dt = time.perf_counter() - t0
+    return {"seconds": dt, "samples_per_s": spec.G * spec.samples / dt, "cores": threads,
+            "kind": "oracle", "sample": f"all {spec.G} points of {spec.name} on {threads} threads"}
+
+
 def cpu_baseline_others(seed=0):
     """The oracle on one host core for the other workloads: the whole
     1000-point plain FP64 scan, the 1e4-point subsample of the 1e8-point
@@ -810,6 +827,12 @@ def main():
         out["cpu_baseline"]["all_host_cores"] = cpu_baseline_threads(spec, args.cpu_points)
         log("cpu baseline: oracle on the other workloads")
         out["cpu_baseline"]["other_workloads"] = cpu_baseline_others()
+        if left(args) > 240:
+            log("cpu baseline: oracle on the whole grid, all host cores")
+            full = cpu_full_grid_threads(spec)
+            full["vs_gpu_step"] = full["seconds"] / (ms_per_step / 1e3)
+            out["cpu_baseline"]["full_grid_all_cores"] = full
+            log(f"  {full['seconds']:.1f} s on {full['cores']} threads")
     else:
         out["cpu_baseline"] = None
     if not args.no_serving:
