@@ -38,9 +38,11 @@
 #include <stdint.h>
 
 /* Environment: ZMC_LOG = 1 reports set-up events on stderr (tune-table
- * loads, batch and server creation, run-time compiles), 2 also every plan and
- * every server admission and completion; unset or 0, the library prints
- * nothing.  ZMC_TUNE_TABLE names the tile-shape table (see the batch API). */
+ * loads, batch and server creation, run-time compiles), 2 also every plan,
+ * every server admission and completion, and every split-partial buffer the
+ * device scan's cache allocates or retires; unset or 0, the library prints
+ * nothing.  ZMC_TUNE_TABLE names the tile-shape table (see the batch API);
+ * ZMC_COPY_THREADS the host threads of chunked scans (zmc_scan_chunked). */
 
 #ifdef __cplusplus
 extern "C" {
@@ -87,8 +89,9 @@ typedef struct zmc_scan_desc {
   const int64_t* axis_len;  /* [M] list lengths L_l                          */
   const double* axis_vals;  /* [sum L_l] host copy of the lists, back to back
                                (finite values; f and sigma are unspecified
-                               for points with a non-finite one); may be
-                               NULL for zmc_scan_device                     */
+                               for points with a non-finite one); read by
+                               the device entry points only when their
+                               d_axis_vals is NULL                          */
   const double* lo;         /* [N] lower box edges                           */
   const double* hi;         /* [N] upper box edges                           */
   int32_t family;           /* zmc_family                                    */
