@@ -299,7 +299,7 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // Split-partial workspaces of zmc_scan_device(_ex).  The stream-ordered
-// allocator of this ROCm makes the calling thread wait, at hipMallocAsync /
+// allocator of HIP 7.2 makes the calling thread wait, at hipMallocAsync /
 // hipFreeAsync, for the device work that last used the block it hands out
 // (measured: each call's enqueue then lasts as long as the previous call's
 // kernels), so back-to-back scans would be serialised on the host.  Outside
