@@ -757,7 +757,8 @@ def main():
     log(f"bench: {spec.name} fp64, steps {args.fp64_steps}")
     r64 = time_path(spec64, args.fp64_steps, 1)
     ms64 = r64["wall_s"] * 1e3 / args.fp64_steps
-    log(f"fp64: {ms64:.3f} ms/step")
+    kern64_ms = float(np.mean(r64["kernel_ms"]))
+    log(f"fp64: {ms64:.3f} ms/step, kernel {kern64_ms:.3f} ms")
 
     from paper_1910_01965_amd import kernel_ids
     ids = kernel_ids.kernel_ids()
@@ -766,6 +767,8 @@ def main():
     if roof["valu_counters"]:
         log(f"roofline: {roof['frac']:.3f} of the VALU peak by operation count, "
             f"{roof['valu_counters']['frac']:.3f} by executed VALU instructions")
+    roof64 = roofline(kernel_ids.GAUSS_F64_N3_POINT_MAJOR, spec.name, spec.family, spec.N, G * n,
+                      kern64_ms, ids, "k_point_major<Gauss<double,3>>")
 
     out = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1,
@@ -777,7 +780,8 @@ def main():
                    "plan": r32["plan"]},
         "grid_pts_per_s": G / (ms_per_step / 1e3),
         "fp64": {"value": G * n / (ms64 / 1e3), "unit": "samples/s", "ms_per_step": ms64,
-                 "grid_pts_per_s": G / (ms64 / 1e3), "steps": args.fp64_steps},
+                 "grid_pts_per_s": G / (ms64 / 1e3), "steps": args.fp64_steps,
+                 "kernel_ms": kern64_ms, "roofline": roof64},
         "latency_ms": {"p50": float(np.percentile(r32["step_ms"], 50)),
                        "p99": float(np.percentile(r32["step_ms"], 99)),
                        "what": "per-scan device time of back-to-back plain scans"},

@@ -99,5 +99,6 @@ def kernel_id(mangled, lib=LIB):
 
 # Mangled names of the kernels that the benchmark reports on.
 GAUSS_F32_N3_POINT_MAJOR = "_ZN3zmc13k_point_majorINS_5GaussIfLi3EEEfLi3EEEvNS_10ScanParamsE"
+GAUSS_F64_N3_POINT_MAJOR = "_ZN3zmc13k_point_majorINS_5GaussIdLi3EEEdLi3EEEvNS_10ScanParamsE"
 COSEXP_F32_N2_POINT_MAJOR = "_ZN3zmc13k_point_majorINS_6CosExpIfLi2EEEfLi2EEEvNS_10ScanParamsE"
 COSEXP_F64_N2_POINT_MAJOR = "_ZN3zmc13k_point_majorINS_6CosExpIdLi2EEEdLi2EEEvNS_10ScanParamsE"

@@ -46,6 +46,7 @@ def test_every_record_was_taken_on_the_built_kernel(ids):
 def test_records_cover_the_bench_kernels(ids):
     have = {(r["kernel"], r["workload"]) for r in bench.counter_records()}
     assert (kernel_ids.GAUSS_F32_N3_POINT_MAJOR, wl.gauss_2p().name) in have
+    assert (kernel_ids.GAUSS_F64_N3_POINT_MAJOR, wl.gauss_2p().name) in have
     assert (kernel_ids.COSEXP_F32_N2_POINT_MAJOR, wl.cosexp_4p().name) in have
 
 
