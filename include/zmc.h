@@ -55,7 +55,8 @@ typedef enum zmc_status {
                             the call would size exceeds 2^56 bytes         */
   ZMC_E_DEVICE = 3,      /* a HIP call failed (no device, launch error)   */
   ZMC_E_UNSUPPORTED = 4, /* valid request the library does not implement  */
-  ZMC_E_BUSY = 5         /* resource limit reached; retry later           */
+  ZMC_E_BUSY = 5,        /* resource limit reached; retry later           */
+  ZMC_E_CANCELLED = 6    /* a served request cancelled before admission   */
 } zmc_status;
 
 /* Integrand families, compiled in as templates.  SIN_SUM is the paper's test
@@ -475,6 +476,8 @@ typedef struct zmc_server_stats {
   uint64_t tickets;            /* requests still tracked: submitted and not yet
                                   released with zmc_server_release           */
   uint64_t slice_samples_now;  /* the sample budget of the next slice        */
+  uint64_t cancelled;          /* requests finished by zmc_server_cancel (also
+                                  counted in failed)                          */
 } zmc_server_stats;
 
 /* Starts the scheduler thread on the current device (opts may be NULL for
@@ -511,6 +514,13 @@ zmc_status zmc_server_wait(zmc_server* server, uint64_t ticket, zmc_status* resu
  * server keeps every unreleased ticket until zmc_server_destroy, so a
  * long-running caller releases each request once it has read its result. */
 zmc_status zmc_server_release(zmc_server* server, uint64_t ticket);
+
+/* Cancels a request that has not been admitted yet: it finishes with status
+ * ZMC_E_CANCELLED (poll and wait report it; its d_f and d_sigma are never
+ * written) and leaves the queue.  ZMC_E_BUSY if it has already been admitted
+ * (it then runs to completion) or has finished; ZMC_E_INVALID for an unknown
+ * ticket.  For callers whose client went away while the request queued. */
+zmc_status zmc_server_cancel(zmc_server* server, uint64_t ticket);
 
 zmc_status zmc_server_get_stats(zmc_server* server, zmc_server_stats* stats);
 

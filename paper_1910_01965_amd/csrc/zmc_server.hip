@@ -62,6 +62,10 @@ struct Request {
   double latency = 0.0;
   zmc_status status = ZMC_OK;
   bool done = false;
+  // under zmc_server::mu: admission is decided (the scheduler sets `admitted`
+  // before any device work of the request), or the request was cancelled
+  bool admitted = false;
+  bool cancelled = false;
 };
 
 using ReqPtr = std::shared_ptr<Request>;
@@ -176,6 +180,7 @@ void finish(zmc_server* s, const ReqPtr& r, zmc_status st) {
     s->t_last_done = Clock::now();
   } else {
     s->stats.failed++;
+    if (st == ZMC_E_CANCELLED) s->stats.cancelled++;
   }
   s->cv_done.notify_all();
 }
@@ -412,6 +417,23 @@ size_t next_pending(const zmc_server* s) {
   return waited * 1e3 > (double)s->opts.max_wait_ms ? oldest : 0;
 }
 
+// Finishes the queued requests that zmc_server_cancel has flagged.
+void drop_cancelled(zmc_server* s) {
+  std::vector<ReqPtr> gone;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (const ReqPtr& r : s->pending)
+      if (r->cancelled) gone.push_back(r);
+  }
+  if (gone.empty()) return;
+  s->pending.erase(std::remove_if(s->pending.begin(), s->pending.end(),
+                                  [&](const ReqPtr& r) {
+                                    return std::find(gone.begin(), gone.end(), r) != gone.end();
+                                  }),
+                   s->pending.end());
+  for (const ReqPtr& r : gone) finish(s, r, ZMC_E_CANCELLED);
+}
+
 void fail_all(zmc_server* s, zmc_status st) {
   for (Slice& sl : s->inflight)
     for (const ReqPtr& r : sl.finishing)
@@ -437,6 +459,7 @@ void run(zmc_server* s) {
       }
       stopping = s->stop;
     }
+    drop_cancelled(s);
     if (broken) {
       fail_all(s, ZMC_E_DEVICE);
       if (stopping) break;
@@ -464,11 +487,25 @@ void run(zmc_server* s) {
       ReqPtr r = s->pending[j];
       if (r->footprint > s->opts.hbm_budget_bytes) {
         s->pending.erase(s->pending.begin() + (std::ptrdiff_t)j);
-        finish(s, r, ZMC_E_NOMEM);
+        bool cancelled;
+        {
+          std::lock_guard<std::mutex> lk(s->mu);
+          cancelled = r->cancelled;
+        }
+        finish(s, r, cancelled ? ZMC_E_CANCELLED : ZMC_E_NOMEM);
         continue;
       }
       if (s->bytes_in_use + r->footprint > s->opts.hbm_budget_bytes) break;
       s->pending.erase(s->pending.begin() + (std::ptrdiff_t)j);
+      {
+        // from here the request is admitted: zmc_server_cancel answers BUSY
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!r->cancelled) r->admitted = true;
+      }
+      if (!r->admitted) {
+        finish(s, r, ZMC_E_CANCELLED);
+        continue;
+      }
       if (r->desc.family == ZMC_USER) {
         // built (first use of this shape) and loaded on the server's device
         const zmc_status us = zmc::user_kernels(r->desc.integrand, r->desc.precision, r->desc.N,
@@ -730,6 +767,22 @@ zmc_status zmc_server_release(zmc_server* s, uint64_t ticket) {
   if (!it->second->done)
     return fail(ZMC_E_BUSY, "request %llu has not finished", (unsigned long long)ticket);
   s->tickets.erase(it);  // a thread still in zmc_server_wait holds its own reference
+  return ok();
+}
+
+zmc_status zmc_server_cancel(zmc_server* s, uint64_t ticket) {
+  if (s == nullptr) return fail(ZMC_E_INVALID, "NULL server");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return fail(ZMC_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+    Request& r = *it->second;
+    if (r.done || r.admitted)
+      return fail(ZMC_E_BUSY, "request %llu has %s", (unsigned long long)ticket,
+                  r.done ? "finished" : "been admitted");
+    r.cancelled = true;
+  }
+  s->cv_work.notify_one();
   return ok();
 }
 

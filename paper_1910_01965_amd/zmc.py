@@ -19,7 +19,7 @@ PRECISION = {"fp64": 0, "fp32": 1}
 MODE = {"auto": 0, "point_major": 1, "sample_major": 2}
 MODE_NAME = {v: k for k, v in MODE.items()}
 STATUS = {0: "ZMC_OK", 1: "ZMC_E_INVALID", 2: "ZMC_E_NOMEM", 3: "ZMC_E_DEVICE",
-          4: "ZMC_E_UNSUPPORTED", 5: "ZMC_E_BUSY"}
+          4: "ZMC_E_UNSUPPORTED", 5: "ZMC_E_BUSY", 6: "ZMC_E_CANCELLED"}
 
 EXPORTS = ("zmc_last_error", "zmc_version", "zmc_validate", "zmc_plan", "zmc_scan",
            "zmc_scan_device", "zmc_scan_device_ex", "zmc_scan_device_noalloc", "zmc_debug_words",
@@ -27,7 +27,7 @@ EXPORTS = ("zmc_last_error", "zmc_version", "zmc_validate", "zmc_plan", "zmc_sca
            "zmc_batch_default_opts", "zmc_batch_plan", "zmc_batch_create", "zmc_batch_launch",
            "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch", "zmc_tune_source",
            "zmc_server_create", "zmc_server_submit", "zmc_server_poll", "zmc_server_wait",
-           "zmc_server_get_stats", "zmc_server_release", "zmc_server_destroy",
+           "zmc_server_get_stats", "zmc_server_release", "zmc_server_cancel", "zmc_server_destroy",
            "zmc_integrand_create", "zmc_integrand_create_ex",
            "zmc_integrand_log", "zmc_integrand_destroy", "zmc_scan_chunked", "zmc_scan_range",
            "zmc_debug_valu_probe", "zmc_debug_rate_probe")
@@ -101,7 +101,8 @@ class ServerStats(ctypes.Structure):
         "slices", "tiles", "bytes_in_use", "bytes_peak")] + [
         (k, ctypes.c_double) for k in ("latency_p50_s", "latency_p99_s", "latency_max_s",
                                        "samples_per_s")] + [("tickets", ctypes.c_uint64),
-                                                            ("slice_samples_now", ctypes.c_uint64)]
+                                                            ("slice_samples_now", ctypes.c_uint64),
+                                                            ("cancelled", ctypes.c_uint64)]
 
 
 _lib = None
@@ -155,6 +156,7 @@ def load():
                                         ctypes.POINTER(ctypes.c_double)]
         lib.zmc_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
         lib.zmc_server_release.argtypes = [vp, ctypes.c_uint64]
+        lib.zmc_server_cancel.argtypes = [vp, ctypes.c_uint64]
         lib.zmc_server_destroy.argtypes = [vp]
         lib.zmc_integrand_create.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
         lib.zmc_integrand_create_ex.argtypes = [ctypes.c_char_p, ctypes.c_uint32, ctypes.POINTER(vp)]
@@ -170,7 +172,7 @@ def load():
                      "zmc_batch_get_info", "zmc_batch_destroy", "zmc_scan_batch",
                      "zmc_server_create", "zmc_server_submit", "zmc_server_poll",
                      "zmc_server_wait", "zmc_server_get_stats", "zmc_server_release",
-                     "zmc_server_destroy"):
+                     "zmc_server_cancel", "zmc_server_destroy"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -632,6 +634,15 @@ class Server:
         outputs (zmc_server_release; raises while it is still running)."""
         _check(load().zmc_server_release(self._h, int(ticket)))
         self._keep.pop(ticket, None)
+
+    def cancel(self, ticket):
+        """Cancels a request that has not been admitted yet (zmc_server_cancel):
+        True if it was, False if it has already been admitted or finished."""
+        st = load().zmc_server_cancel(self._h, ctypes.c_uint64(int(ticket)))
+        if st == 5:
+            return False
+        _check(st)
+        return True
 
     def poll(self, ticket):
         """(done, status, latency_s)."""

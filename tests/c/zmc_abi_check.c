@@ -194,6 +194,13 @@ int main(int argc, char** argv) {
   d.seed = 42;
 
   printf("library: %s\n", zmc_version());
+  /* the layouts a binding must mirror */
+  printf("sizeof: scan_desc %zu launch_opts %zu plan_info %zu batch_opts %zu batch_info %zu "
+         "server_opts %zu server_stats %zu\n",
+         sizeof(zmc_scan_desc), sizeof(zmc_launch_opts), sizeof(zmc_plan_info),
+         sizeof(zmc_batch_opts), sizeof(zmc_batch_info), sizeof(zmc_server_opts),
+         sizeof(zmc_server_stats));
+  expect(zmc_server_cancel(NULL, 1) == ZMC_E_INVALID, "zmc_server_cancel: NULL server");
   uint64_t G = 0;
   expect(zmc_validate(&d, &G) == ZMC_OK && G == G_ALL, "zmc_validate: a 40 x 30 GAUSS grid");
   zmc_scan_desc bad = d;

@@ -312,6 +312,17 @@ def test_c_program_uses_the_abi_without_python():
     r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "passed (host-only part)" in r.stdout
+    # the Python binding's structures have the C layouts
+    import ctypes as ct
+    sizes = dict(zip(*[iter(next(ln for ln in r.stdout.splitlines()
+                                  if ln.startswith("sizeof:")).split()[1:])] * 2))
+    assert int(sizes["scan_desc"]) == ct.sizeof(zmc.ScanDesc)
+    assert int(sizes["launch_opts"]) == ct.sizeof(zmc.LaunchOpts)
+    assert int(sizes["plan_info"]) == ct.sizeof(zmc.PlanInfo)
+    assert int(sizes["batch_opts"]) == ct.sizeof(zmc.BatchOpts)
+    assert int(sizes["batch_info"]) == ct.sizeof(zmc.BatchInfo)
+    assert int(sizes["server_opts"]) == ct.sizeof(zmc.ServerOpts)
+    assert int(sizes["server_stats"]) == ct.sizeof(zmc.ServerStats)
 
 
 def test_server_rejects_bad_admission_options(lib):

@@ -161,15 +161,22 @@ def test_shutdown_drains_pending_requests():
 
 def test_one_slot_serves_in_arrival_order():
     """With one slot the server admits requests in submission order: each
-    completes after the one before it (latencies, measured from each one's
-    submission, do not decrease for requests submitted together), poll agrees
-    with wait, and the statistics count every request once (the pending and
-    active gauges are refreshed by the scheduler loop after the wake-up, so
-    they are not read here)."""
+    completes after the one before it, poll agrees with wait, and the
+    statistics count every request once (the pending and active gauges are
+    refreshed by the scheduler loop after the wake-up, so they are not read
+    here).  A request's completion time is its submission time plus its
+    latency; the submission happens inside the submit call, whose start and
+    end the host clock brackets (the library's clock is the same monotonic
+    clock), so request i cannot have completed after request i + 1 if the
+    earliest completion time of i is after the latest of i + 1."""
     zmc = _zmc()
-    specs = _requests(8, seed=11, max_samples=1 << 12)
+    specs = _requests(8, seed=11, max_samples=1 << 14)
     srv = zmc.Server(max_slots=1)
-    tickets = [srv.submit(sp) for sp in specs]
+    tickets, spans = [], []
+    for sp in specs:
+        t0 = time.monotonic()
+        tickets.append(srv.submit(sp))
+        spans.append((t0, time.monotonic()))
     lat = []
     for t in tickets:
         st, l = srv.wait(t)
@@ -177,8 +184,10 @@ def test_one_slot_serves_in_arrival_order():
         done, st2, l2 = srv.poll(t)
         assert done and st2 == 0 and l2 == l
         lat.append(l)
+    earliest = [a + l for (a, _), l in zip(spans, lat)]
+    latest = [b + l for (_, b), l in zip(spans, lat)]
     _say(f"one-slot latencies {['%.4f' % x for x in lat]}")
-    assert all(b >= a for a, b in zip(lat, lat[1:]))
+    assert all(earliest[i] <= latest[i + 1] for i in range(len(specs) - 1)), (earliest, latest)
     stats = srv.stats()
     assert stats["submitted"] == stats["admitted"] == stats["completed"] == len(specs)
     assert stats["failed"] == 0
@@ -336,3 +345,45 @@ def test_slice_duration_target():
     for i in (0, 7):
         fa, sa = _alone(specs[i])
         assert np.array_equal(runs[1000][1][i][0], fa) and np.array_equal(runs[1000][1][i][1], sa)
+
+
+def test_cancel_a_queued_request():
+    """zmc_server_cancel: a request still queued finishes with ZMC_E_CANCELLED,
+    its outputs untouched; an admitted or finished one cannot be cancelled;
+    the other requests complete bitwise as alone."""
+    import torch
+    zmc = _zmc()
+    big = wl.gauss_2p(points_per_axis=1000, samples=1 << 16, precision="fp32")
+    small = _requests(5, seed=11, max_samples=1 << 12)
+    _say("cancel: one slot, a large request ahead of five small ones")
+    srv = zmc.Server(max_slots=1)
+    t_big = srv.submit(big)
+    deadline = time.time() + 30.0
+    while srv.stats()["admitted"] < 1:               # the large request holds the slot
+        assert time.time() < deadline
+        time.sleep(0.001)
+    assert srv.cancel(t_big) is False               # admitted: it runs to completion
+    f3 = torch.full((small[3].G,), float("nan"), dtype=torch.float64, device="cuda")
+    s3 = torch.full_like(f3, float("nan"))
+    torch.cuda.synchronize()
+    tickets = [srv.submit(sp) if i != 3 else srv.submit(sp, f=f3, sigma=s3)
+               for i, sp in enumerate(small)]
+    assert srv.cancel(tickets[3]) is True           # still queued behind the large one
+    assert srv.wait(tickets[3])[0] == 6             # ZMC_E_CANCELLED
+    with pytest.raises(zmc.ZmcError) as ei:
+        srv.cancel(10 ** 9)
+    assert ei.value.status == 1
+    assert srv.wait(t_big)[0] == 0
+    for i, t in enumerate(tickets):
+        if i != 3:
+            assert srv.wait(t)[0] == 0
+    assert srv.cancel(tickets[0]) is False          # finished
+    stats = srv.stats()
+    assert stats["cancelled"] == 1 and stats["failed"] == 1 and stats["completed"] == 5
+    outs = {i: srv.outputs(t) for i, t in enumerate(tickets) if i != 3}
+    srv.close()
+    torch.cuda.synchronize()
+    assert torch.isnan(f3).all() and torch.isnan(s3).all()
+    for i in (0, 4):
+        fa, sa = _alone(small[i])
+        assert np.array_equal(outs[i][0].cpu().numpy(), fa) and np.array_equal(outs[i][1].cpu().numpy(), sa)
