@@ -29,7 +29,9 @@
  *     other pointers are host memory; all are owned by the caller and read or
  *     written only during the call (for asynchronous calls: until the work on
  *     the given stream has completed);
- *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *   - the host side of the scan, batch, range and server entry points is
+ *     marked with ROCTx ranges named after them, for rocprofv3 --marker-trace.
  */
 #ifndef ZMC_H
 #define ZMC_H
@@ -174,8 +176,9 @@ zmc_status zmc_scan(const zmc_scan_desc* desc, double* f, double* sigma);
  * stream capture that gives ZMC_E_INVALID (a replay cannot re-read host
  * memory), and with both pointers NULL too.
  * Split partials, when the plan needs them (16 B per point and sample
- * piece), come from a per-device cache of at most four buffers of up to
- * 256 MB each, held by the library until the process ends and reused
+ * piece), come from a per-device cache of at most four buffers of
+ * power-of-two sizes from 1 MiB to 256 MB, held by the library until the
+ * process ends and reused
  * without a host wait (a buffer still in use by another call's kernels is
  * ordered after them on the device); larger partials, and every call made
  * under stream capture, live in stream-ordered device memory released on

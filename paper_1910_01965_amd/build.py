@@ -88,7 +88,8 @@ def build(out=LIB, jobs=None, verbose=False):
         objs = list(ex.map(compile_one, SOURCES))
     tmp = out + ".tmp"
     subprocess.run([cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, f"-L{ROCM}/lib",
-                    "-lhiprtc", f"-Wl,-rpath,{ROCM}/lib", "-o", tmp], check=True)
+                    "-lhiprtc", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM}/lib", "-o", tmp],
+                   check=True)
     os.replace(tmp, out)
     return out
 

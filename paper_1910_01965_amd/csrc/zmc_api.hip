@@ -14,6 +14,7 @@
 #include "zmc.h"
 #include "zmc_device.hpp"
 #include "zmc_internal.hpp"
+#include "zmc_trace.hpp"
 
 namespace {
 thread_local char g_err[512] = "";
@@ -304,8 +305,9 @@ namespace {
 // (measured: each call's enqueue then lasts as long as the previous call's
 // kernels), so back-to-back scans would be serialised on the host.  Outside
 // stream capture, workspaces of up to kMaxCachedWorkspace bytes therefore come
-// from a small per-device cache, without a host wait: each buffer carries an
-// event recorded after the last kernel that uses it and that kernel's stream.
+// from a small per-device cache, without a host wait: buffers of power-of-two
+// sizes from 1 MiB, each with an event recorded after the last kernel that
+// uses it and that kernel's stream.
 // A call takes, among the buffers large enough, one whose event has completed;
 // else one last used on the same stream; else a new one while the device holds
 // fewer than kMaxCachedBuffers; else any.  A buffer whose event is pending is
@@ -377,10 +379,16 @@ hipError_t ws_acquire(int dev, size_t bytes, hipStream_t s, Workspace* out) {
     (void)hipEventDestroy(drop.done);
     (void)hipFree(drop.ptr);
   }
-  zmc::log(2, "workspace: new %zu-byte buffer on device %d", bytes, dev);
+  // power-of-two sizes from 1 MiB: a buffer then also serves the smaller
+  // workspaces of later calls, so a mix of sizes settles on a few buffers
+  // instead of retiring (and freeing, which waits for the device) one per call
+  size_t size = (size_t)1 << 20;
+  while (size < bytes) size <<= 1;
+  if (size > kMaxCachedWorkspace) size = bytes;
+  zmc::log(2, "workspace: new %zu-byte buffer on device %d", size, dev);
   Workspace w;
-  w.bytes = bytes;
-  hipError_t e = hipMalloc(&w.ptr, bytes);
+  w.bytes = size;
+  hipError_t e = hipMalloc(&w.ptr, size);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&w.done, hipEventDisableTiming);
   if (e != hipSuccess) {
     if (w.ptr) (void)hipFree(w.ptr);
@@ -444,6 +452,7 @@ zmc_status zmc_plan(const zmc_scan_desc* desc, const zmc_launch_opts* opts, zmc_
 
 zmc_status zmc_scan_device_ex(const zmc_scan_desc* desc, const double* d_axis_vals, double* d_f,
                               double* d_sigma, const zmc_launch_opts* opts, void* stream) {
+  zmc::TraceRange trace_range("zmc_scan_device");
   uint64_t G = 0;
   zmc_status st = validate(desc, &G);
   if (st != ZMC_OK) return st;
@@ -573,6 +582,7 @@ extern "C" {
 
 zmc_status zmc_scan_device_noalloc(const zmc_scan_desc* desc, const double* d_axis_vals,
                                    double* d_f, double* d_sigma, void* stream) {
+  zmc::TraceRange trace_range("zmc_scan_device_noalloc");
   uint64_t G = 0;
   zmc_status st = validate(desc, &G);
   if (st != ZMC_OK) return st;
@@ -608,6 +618,7 @@ zmc_status zmc_scan_device_noalloc(const zmc_scan_desc* desc, const double* d_ax
 }
 
 zmc_status zmc_scan(const zmc_scan_desc* desc, double* f, double* sigma) {
+  zmc::TraceRange trace_range("zmc_scan");
   uint64_t G = 0;
   zmc_status st = validate(desc, &G);
   if (st != ZMC_OK) return st;
@@ -727,6 +738,7 @@ zmc_status zmc_scan_chunked(const zmc_scan_desc* desc, double* f, double* sigma,
 
 zmc_status zmc_scan_range(const zmc_scan_desc* desc, uint64_t g_begin, uint64_t g_end, double* f,
                           double* sigma, uint64_t chunk_points) {
+  zmc::TraceRange trace_range("zmc_scan_range");
   uint64_t G = 0;
   zmc_status st = validate(desc, &G);
   if (st != ZMC_OK) return st;
@@ -807,6 +819,7 @@ zmc_status zmc_scan_range(const zmc_scan_desc* desc, uint64_t g_begin, uint64_t 
   const uint64_t chunks = (R + C - 1) / C;
   uint64_t prev_g0 = 0, prev_n = 0;
   for (uint64_t i = 0; e == hipSuccess && i < chunks; ++i) {
+    zmc::TraceRange chunk_range("zmc_scan_range chunk");
     const int slot = (int)(i & 1);
     const uint64_t g0 = i * C, n = std::min<uint64_t>(C, R - g0);  // g0: offset in the range
     double* d_f = (double*)(dmem + off_out + (size_t)slot * slot_bytes);

@@ -17,6 +17,7 @@
 #include "zmc.h"
 #include "zmc_device.hpp"
 #include "zmc_internal.hpp"
+#include "zmc_trace.hpp"
 
 using zmc::fail;
 using zmc::ok;
@@ -313,6 +314,7 @@ zmc_status zmc_batch_plan(const zmc_scan_desc* scans, int32_t n_scans, const zmc
 zmc_status zmc_batch_create(const zmc_scan_desc* scans, int32_t n_scans,
                             const double* const* d_axis_vals, double* const* d_f,
                             double* const* d_sigma, const zmc_batch_opts* opts, zmc_batch** out) {
+  zmc::TraceRange trace_range("zmc_batch_create");
   if (out == nullptr) return fail(ZMC_E_INVALID, "out is NULL");
   *out = nullptr;
   if (d_f == nullptr || d_sigma == nullptr) return fail(ZMC_E_INVALID, "d_f or d_sigma is NULL");
@@ -457,6 +459,7 @@ zmc_status zmc_batch_create(const zmc_scan_desc* scans, int32_t n_scans,
 }
 
 zmc_status zmc_batch_launch(zmc_batch* b, void* stream) {
+  zmc::TraceRange trace_range("zmc_batch_launch");
   if (b == nullptr) return fail(ZMC_E_INVALID, "batch is NULL");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;

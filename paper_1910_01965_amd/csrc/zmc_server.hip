@@ -29,6 +29,7 @@
 #include "zmc.h"
 #include "zmc_device.hpp"
 #include "zmc_internal.hpp"
+#include "zmc_trace.hpp"
 
 using zmc::fail;
 using zmc::ok;
@@ -187,6 +188,7 @@ void finish(zmc_server* s, const ReqPtr& r, zmc_status st) {
 
 // Admission: device state, staged lists, the slot's scan descriptor.
 hipError_t admit(zmc_server* s, const ReqPtr& r, int si) {
+  zmc::TraceRange trace_range("zmc_server admit");
   hipStream_t st = s->streams[si];
   hipError_t e = hipSuccess;
   if (r->footprint > 0) e = hipMallocAsync(&r->dmem, r->footprint, st);
@@ -231,6 +233,7 @@ bool same_variant(const Request& a, const Request& b) {
 // are sized in samples, not tiles, because a request's tiles range from one
 // point's sample piece to 256 points' pieces.
 hipError_t launch_slice(zmc_server* s, int si, Slice* out) {
+  zmc::TraceRange trace_range("zmc_server slice");
   const uint64_t cap = (uint64_t)s->opts.slice_tiles;
   const uint64_t budget = s->slice_budget;
   const int ring_slot = (int)(s->slice_count % (uint64_t)s->ring);
@@ -683,6 +686,7 @@ zmc_status zmc_server_create(const zmc_server_opts* opts, zmc_server** out) {
 
 zmc_status zmc_server_submit(zmc_server* s, const zmc_scan_desc* desc, const double* d_axis_vals,
                              double* d_f, double* d_sigma, uint64_t* ticket) {
+  zmc::TraceRange trace_range("zmc_server_submit");
   if (s == nullptr || ticket == nullptr) return fail(ZMC_E_INVALID, "NULL server or ticket");
   uint64_t G = 0;
   zmc_status st = zmc::validate_desc(desc, &G);

@@ -122,3 +122,26 @@ def test_workspace_allocations_are_logged():
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [ln for ln in r.stderr.splitlines() if ln.startswith("[zmc] workspace: new")]
     assert len(lines) == 1, r.stderr[-2000:]        # the three scans share one buffer
+
+
+def test_mixed_sizes_settle_on_few_buffers():
+    """Back-to-back scans whose workspaces range over 0.16..16 MB in shuffled
+    order: buffers come in power-of-two sizes, so a larger one serves later
+    smaller calls and the cache allocates at most one buffer per size class
+    (1, 2, 4, 8, 16 MiB) instead of one per call."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import numpy as np, torch\n"
+            "from paper_1910_01965_amd import zmc, workloads as wl\n"
+            "rng = np.random.default_rng(5)\n"
+            "for p in rng.integers(50, 500, size=40):\n"
+            "    zmc.scan(wl.gauss_2p(points_per_axis=int(p), samples=1029), mode='point_major',"
+            " splits=4)\n"
+            "torch.cuda.synchronize()\n")
+    print("workspace sizes of a shuffled mix in a child process", flush=True)
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=dict(os.environ, ZMC_LOG="2"),
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    new = [ln for ln in r.stderr.splitlines() if ln.startswith("[zmc] workspace: new")]
+    assert 1 <= len(new) <= 5, "\n".join(new)
