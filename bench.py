@@ -252,7 +252,7 @@ def batched_run(reps=1, count=512, seed=3):
 
 
 def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=0, compare_plain=False,
-                admission="fifo", verify=0):
+                admission="fifo", verify=0, slice_us=0):
     """Poisson arrivals of scans shaped like the 512-scan batch (family,
     N, grid size, samples drawn by default_rng(seed); request i has Philox
     seed i) into the continuous-batching server; latency = completion -
@@ -270,7 +270,8 @@ def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=0, compare_pl
     n_req = len(t_arr)
     specs = [sp.with_(seed=i) for i, sp in enumerate(wl.batched_512(count=n_req, seed=seed))]
     total = sum(sp.G * sp.samples for sp in specs)
-    srv = zmc.Server(hbm_budget_bytes=budget, max_slots=max_slots, admission=admission)
+    srv = zmc.Server(hbm_budget_bytes=budget, max_slots=max_slots, admission=admission,
+                     slice_us=slice_us)
     tickets = []
     t0 = time.perf_counter()
     for ta, sp in zip(t_arr, specs):
@@ -303,7 +304,7 @@ def serving_run(rate, duration, seed=7, budget=64 << 30, max_slots=0, compare_pl
                          "mean": float(lat.mean()), "max": float(lat.max())},
            "slices": stats["slices"], "bytes_peak": stats["bytes_peak"],
            "budget_bytes": budget, "max_slots": max_slots if max_slots > 0 else 256,
-           "admission": admission, "roofline": mix_roofline(specs, t_all),
+           "admission": admission, "slice_us": slice_us, "roofline": mix_roofline(specs, t_all),
            "server_reported": {k: stats[k] for k in ("latency_p50_s", "latency_p99_s",
                                                      "latency_max_s", "samples_per_s")}}
     if served:
@@ -681,11 +682,27 @@ def serving_section(args, out):
     log(f"serving steady: {steady_rate:.1f} req/s for {args.serve_steady_seconds} s")
     steady = serving_run(steady_rate, args.serve_steady_seconds, seed=8,
                          max_slots=args.serve_max_slots)
+    log(f"serving steady: p50 {steady['latency_s']['p50'] * 1e3:.1f} ms, "
+        f"p99 {steady['latency_s']['p99'] * 1e3:.1f} ms")
     slots = args.serve_max_slots if args.serve_max_slots > 0 else 256
-    return {"overload_200_per_s": over, "overload_200_per_s_shortest_first": short,
-            "steady_0p7_capacity": steady,
-            "what": f"Poisson arrivals of 512-batch-shaped scans, 64 GiB budget, {slots} slots; "
-                    "latency = completion - submission"}
+    out_s = {"overload_200_per_s": over, "overload_200_per_s_shortest_first": short,
+             "steady_0p7_capacity": steady}
+    if args.slice_sweep:
+        # the same steady arrivals with slices sized for a target device time
+        # (zmc_server_opts.slice_us; 0 = the default 4e9-sample slices)
+        out_s["steady_slice_sweep"] = []
+        for us in (int(x) for x in args.slice_sweep.split(",")):
+            r = serving_run(steady_rate, args.serve_steady_seconds, seed=8,
+                            max_slots=args.serve_max_slots, slice_us=us)
+            log(f"serving steady, slice_us={us}: p50 {r['latency_s']['p50'] * 1e3:.1f} ms, "
+                f"p99 {r['latency_s']['p99'] * 1e3:.1f} ms, {r['slices']} slices, "
+                f"{r['value']:.4g} samples/s")
+            out_s["steady_slice_sweep"].append(
+                {"slice_us": us, "latency_s": r["latency_s"], "slices": r["slices"],
+                 "value": r["value"], "requests": r["requests"], "rate_per_s": r["rate_per_s"]})
+    out_s["what"] = (f"Poisson arrivals of 512-batch-shaped scans, 64 GiB budget, {slots} slots; "
+                     "latency = completion - submission")
+    return out_s
 
 
 def main():
@@ -710,6 +727,9 @@ def main():
                     help="arrival window of the shortest-first run (at most --serve-seconds)")
     ap.add_argument("--serve-steady-seconds", type=float, default=8.0,
                     help="arrival window of the steady run at 0.7x capacity")
+    ap.add_argument("--slice-sweep", default="",
+                    help="comma-separated slice_us targets: the steady run again with each "
+                         "(0 = the default slices); off by default")
     ap.add_argument("--serve-max-slots", type=int, default=0,
                     help="admitted requests at once (0 = the server's default, 256)")
     ap.add_argument("--time-budget", type=float, default=540.0,
