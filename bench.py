@@ -491,6 +491,47 @@ def valu_probe(blocks=65536, iters=512, reps=3):
                                      "vs_single_issue_peak": fmas / t / (VALU_PEAK / 2)}}), flush=True)
 
 
+def dims_sweep(samples=1 << 12, steps=3):
+    """Roofline fraction of the point-major kernels across the integration
+    dimension, up to the descriptor's 16: GAUSS and SIN_SUM on a 1000 x 1000
+    grid and COSEXP on 32^4 points, 4096 samples per point, both precisions;
+    algorithmic operations per sample as in the main line, kernel time from
+    HIP events.  One JSON line."""
+    import torch
+    from paper_1910_01965_amd import workloads as wl
+    from paper_1910_01965_amd import zmc
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    zmc.load()
+    ax = np.linspace(0.1, 10.0, 1000)
+    rows = []
+    for fam, N in (("gauss", 3), ("gauss", 8), ("gauss", 12), ("gauss", 16), ("sin_sum", 8),
+                   ("sin_sum", 16), ("cosexp", 16)):
+        for prec in ("fp32", "fp64"):
+            if fam == "gauss":
+                sp = wl.ScanSpec("gauss", [ax, ax.copy()], np.zeros(N), np.ones(N), samples, 42, prec)
+            elif fam == "sin_sum":
+                sp = wl.ScanSpec("sin_sum", [np.linspace(0, 1, 1000)] * 2, np.zeros(N), np.ones(N),
+                                 samples, 42, prec)
+            else:
+                hi = np.ones(N)
+                hi[0] = 2.0
+                sp = wl.ScanSpec("cosexp", [np.linspace(-1, 1, 32)] * 4, np.zeros(N), hi, samples, 42,
+                                 prec)
+            r = time_path(sp, steps, 1)
+            km = float(np.mean(r["kernel_ms"]))
+            w = valu_ops_per_sample(fam, N)
+            row = {"family": fam, "N": N, "precision": prec, "grid_points": sp.G, "samples": samples,
+                   "kernel_ms": km, "samples_per_s": sp.G * samples / (km / 1e3),
+                   "ops_per_sample": w, "frac": w * sp.G * samples / (km / 1e3) / VALU_PEAK,
+                   "plan": r["plan"]}
+            rows.append(row)
+            log(f"{fam} N={N} {prec}: {km:.2f} ms, {row['samples_per_s']:.3g} samples/s, "
+                f"frac {row['frac']:.3f}")
+    print(json.dumps({"dims_sweep": rows, "peak": VALU_PEAK / 1e12, "unit": "T lane-op/s"}),
+          flush=True)
+
+
 def rate_probe(blocks=8192, iters=1024, reps=3):
     """Issue rate of each instruction form the scan kernels use
     (zmc_debug_rate_probe): lane-instructions per second, and that rate over
@@ -739,6 +780,8 @@ def main():
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--valu-probe", action="store_true",
                     help="only run the FMA-chain load (VALU counter calibration)")
+    ap.add_argument("--dims-sweep", action="store_true",
+                    help="only time the point-major kernels across N = 3..16 (roofline fractions)")
     ap.add_argument("--rate-probe", action="store_true",
                     help="only time the instruction-rate loads of the scan kernels' op mix")
     args = ap.parse_args()
@@ -750,6 +793,9 @@ def main():
         return
     if args.rate_probe:
         rate_probe()
+        return
+    if args.dims_sweep:
+        dims_sweep()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the scan shards by "
