@@ -491,12 +491,13 @@ def valu_probe(blocks=65536, iters=512, reps=3):
                                      "vs_single_issue_peak": fmas / t / (VALU_PEAK / 2)}}), flush=True)
 
 
-def dims_sweep(samples=1 << 12, steps=3):
+def dims_sweep(samples=1 << 12, steps=10, warmup=5):
     """Roofline fraction of the point-major kernels across the integration
     dimension, up to the descriptor's 16: GAUSS and SIN_SUM on a 1000 x 1000
     grid and COSEXP on 32^4 points, 4096 samples per point, both precisions;
     algorithmic operations per sample as in the main line, kernel time from
-    HIP events.  One JSON line."""
+    HIP events after `warmup` scans (kernels of a few ms run slower until the
+    device has been busy for a while).  One JSON line."""
     import torch
     from paper_1910_01965_amd import workloads as wl
     from paper_1910_01965_amd import zmc
@@ -518,7 +519,7 @@ def dims_sweep(samples=1 << 12, steps=3):
                 hi[0] = 2.0
                 sp = wl.ScanSpec("cosexp", [np.linspace(-1, 1, 32)] * 4, np.zeros(N), hi, samples, 42,
                                  prec)
-            r = time_path(sp, steps, 1)
+            r = time_path(sp, steps, warmup)
             km = float(np.mean(r["kernel_ms"]))
             w = valu_ops_per_sample(fam, N)
             row = {"family": fam, "N": N, "precision": prec, "grid_points": sp.G, "samples": samples,
